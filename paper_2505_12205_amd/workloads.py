@@ -1,0 +1,188 @@
+"""Seeded synthetic workloads: lattice-unit parameters and initial fields.
+
+This module is the only code shared by the HIP path and the FP64 oracle.  It
+holds no step arithmetic: it produces plain parameter dictionaries and initial
+phase-field / velocity arrays (layout [z, y, x], x fastest) from which each
+side builds its own initial populations.
+
+Parameter values follow the dimensionless groups of the paper's validation
+and jet sections (density ratio, viscosity ratio, Reynolds, Weber, Froude,
+Atwood, Peclet and capillary numbers) converted to lattice units with
+nu = tau cs^2, cs^2 = 1/3.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CS2 = 1.0 / 3.0
+
+
+def _tanh_profile(signed_dist, xi):
+    """Equilibrium kernel of the phase field: 1/2 + 1/2 tanh(2 d / xi)."""
+    return 0.5 + 0.5 * np.tanh(2.0 * signed_dist / xi)
+
+
+def _grid(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x.astype(np.float64), y.astype(np.float64), z.astype(np.float64)
+
+
+def perturb(phi0, u0, seed, phi_amp=0.0, u_amp=0.0):
+    """Seeded noise added to initial fields (breaks exact symmetries in parity runs)."""
+    rng = np.random.default_rng(seed)
+    phi = phi0 + phi_amp * rng.standard_normal(phi0.shape) if phi_amp else phi0.copy()
+    if u_amp:
+        un = u_amp * rng.standard_normal((3,) + phi0.shape)
+        u = un if u0 is None else u0 + un
+    else:
+        u = None if u0 is None else u0.copy()
+    return phi, u
+
+
+# --------------------------------------------------------------------------
+# 2D stationary drop (D2Q9, all periodic)
+# --------------------------------------------------------------------------
+
+def drop2d(n=128, radius=25.0, xi=4.0, rho_h=1.0, rho_l=1e-3, visc_ratio=100.0,
+           nu_h=0.1, sigma=1e-4, mobility=0.02, center=None, kinematic_ratio=True):
+    """Heavy drop of radius R centred in an n x n periodic box.
+
+    The viscosity ratio is kinematic, nu_H / nu_L = visc_ratio, by default:
+    tau_H = nu_H / cs^2, tau_L = nu_L / cs^2.  (Read as a dynamic ratio
+    mu_H / mu_L = 100 at rho_H / rho_L = 1000 it gives nu_L = 1.0; the explicit
+    viscous force then moves information across the light side of the
+    interface at about 4 nu_L / xi = 1 lattice unit per step and the scheme
+    diverges.)  kinematic_ratio=False selects the dynamic reading."""
+    if kinematic_ratio:
+        nu_l = nu_h / visc_ratio
+    else:
+        nu_l = (rho_h * nu_h / visc_ratio) / rho_l
+    cfg = dict(q=9, nx=n, ny=n, nz=1, rho_h=rho_h, rho_l=rho_l,
+               tau_h=nu_h / CS2, tau_l=nu_l / CS2,
+               sigma=sigma, xi=xi, mobility=mobility,
+               gravity=(0.0, 0.0, 0.0), body_force="rho", bc=("periodic",) * 6,
+               name=f"drop2d_{n}x{n}_R{radius:g}")
+    cx, cy = center if center is not None else (n / 2.0, n / 2.0)
+    x, y, _ = _grid(n, n, 1)
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    phi0 = _tanh_profile(radius - r, xi)
+    return cfg, phi0, None
+
+
+# --------------------------------------------------------------------------
+# 3D Rayleigh-Taylor (D3Q19; periodic x/z, no-slip walls in y)
+# --------------------------------------------------------------------------
+
+def rt_params(lref=256, atwood=0.5, reynolds=3000.0, u0=0.04, visc_ratio=1.0,
+              peclet=1000.0, capillary=0.26, xi=5.0):
+    """Lattice-unit parameters of the Rayleigh-Taylor case.
+
+    U0 = sqrt(g L) (given), At = (rho_H - rho_L)/(rho_H + rho_L), Re = rho_H U0 L / mu_H,
+    Pe = U0 L / M, Ca = mu_H U0 / sigma, with rho_H = 1."""
+    rho_h = 1.0
+    rho_l = rho_h * (1.0 - atwood) / (1.0 + atwood)
+    mu_h = rho_h * u0 * lref / reynolds
+    mu_l = mu_h / visc_ratio
+    g = u0 * u0 / lref
+    return dict(rho_h=rho_h, rho_l=rho_l, tau_h=(mu_h / rho_h) / CS2,
+                tau_l=(mu_l / rho_l) / CS2, mobility=u0 * lref / peclet,
+                sigma=mu_h * u0 / capillary, xi=xi, g=g)
+
+
+def rt3d(nx=256, ny=1024, nz=256, lref=256, amp_frac=0.1, **kw):
+    """Heavy fluid above a cosine-perturbed interface y0(x, z) in a
+    nx x ny x nz box; parameters from rt_params(lref) so that a small copy
+    (nx < lref) carries the same per-node arithmetic as the full case.
+    y0 = ny/2 + amp_frac/2 * nx [cos(2 pi x/nx) + cos(2 pi z/nz)], peak amp_frac * nx."""
+    p = rt_params(lref=lref, **kw)
+    cfg = dict(q=19, nx=nx, ny=ny, nz=nz, rho_h=p["rho_h"], rho_l=p["rho_l"],
+               tau_h=p["tau_h"], tau_l=p["tau_l"], sigma=p["sigma"], xi=p["xi"],
+               mobility=p["mobility"], gravity=(0.0, -p["g"], 0.0),
+               body_force="rho_minus_rhol",
+               bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
+               name=f"rt3d_{nx}x{ny}x{nz}")
+    x, y, z = _grid(nx, ny, nz)
+    y0 = ny / 2.0 + 0.5 * amp_frac * nx * (np.cos(2 * np.pi * x / nx) + np.cos(2 * np.pi * z / nz))
+    phi0 = _tanh_profile(y - y0, p["xi"])
+    return cfg, phi0, None
+
+
+# --------------------------------------------------------------------------
+# 3D liquid jet (D3Q19; free-slip sides, circular velocity inlet at z = 0,
+# convective outlet at z = nz - 1, gravity along +z)
+# --------------------------------------------------------------------------
+
+def jet_params(diameter, u_jet=0.02, rho_ratio=800.0, visc_ratio=50.0, reynolds=300.0,
+               weber=5.0, fr_over_re=0.01728, xi=5.0, mobility=0.01):
+    """Re = rho_H u_j D / mu_H, We = rho_H u_j^2 D / sigma, Fr = u_j / sqrt(g D)
+    with Fr/Re fixed (the constant ratio across the paper's jet table)."""
+    rho_h = 1.0
+    rho_l = rho_h / rho_ratio
+    mu_h = rho_h * u_jet * diameter / reynolds
+    mu_l = mu_h / visc_ratio
+    froude = fr_over_re * reynolds
+    g = u_jet * u_jet / (froude * froude * diameter)
+    return dict(rho_h=rho_h, rho_l=rho_l, tau_h=(mu_h / rho_h) / CS2,
+                tau_l=(mu_l / rho_l) / CS2, sigma=rho_h * u_jet * u_jet * diameter / weber,
+                xi=xi, mobility=mobility, g=g, u_jet=u_jet)
+
+
+def jet3d(nx=192, ny=192, nz=768, radius=12.0, stub=16.0, **kw):
+    """Jet domain with the nozzle centred in the inlet face; the liquid column
+    initially fills z < stub inside the nozzle radius and moves at u_j."""
+    p = jet_params(2.0 * radius, **kw)
+    cx, cy = nx / 2.0, ny / 2.0
+    cfg = dict(q=19, nx=nx, ny=ny, nz=nz, rho_h=p["rho_h"], rho_l=p["rho_l"],
+               tau_h=p["tau_h"], tau_l=p["tau_l"], sigma=p["sigma"], xi=p["xi"],
+               mobility=p["mobility"], gravity=(0.0, 0.0, p["g"]),
+               body_force="rho_minus_rhol",
+               bc=("freeslip", "freeslip", "freeslip", "freeslip", "inlet", "outlet"),
+               inlet_center=(cx, cy), inlet_radius=radius, inlet_u=p["u_jet"],
+               outlet_mode="local", name=f"jet3d_{nx}x{ny}x{nz}_R{radius:g}")
+    x, y, z = _grid(nx, ny, nz)
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    phi0 = _tanh_profile(radius - r, p["xi"]) * _tanh_profile(stub - z, p["xi"])
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[2] = p["u_jet"] * phi0
+    return cfg, phi0, u0
+
+
+def sweep_lengths(seed=12205, n=64, lo=256, hi=768):
+    """Domain lengths of the batched Weber sweep (uniform integers in [lo, hi])."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, n)
+
+
+def sweep_weber(n=64, lo=0.5, hi=8.0):
+    """Log-spaced Weber numbers We_k = lo * (hi/lo)^(k/(n-1))."""
+    return lo * (hi / lo) ** (np.arange(n) / (n - 1))
+
+
+def jet_sweep(n=64, nx=96, ny=96, radius=8.0, reynolds=200.0, lengths=None, webers=None,
+              seed=12205):
+    """The batched sweep: a list of (cfg, phi0, u0) jet domains of uneven length."""
+    L = sweep_lengths(seed, n) if lengths is None else lengths
+    We = sweep_weber(n) if webers is None else webers
+    out = []
+    for k in range(len(L)):
+        out.append(jet3d(nx=nx, ny=ny, nz=int(L[k]), radius=radius, reynolds=reynolds,
+                         weber=float(We[k])))
+    return out
+
+
+def phi_in_profile(cfg):
+    """Nozzle profile psi(r) on the inlet face (for diagnostics)."""
+    x, y, _ = _grid(cfg["nx"], cfg["ny"], 1)
+    cx, cy = cfg["inlet_center"]
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    return _tanh_profile(cfg["inlet_radius"] - r, cfg["xi"])[0]
+
+
+def summary(cfg):
+    """Human-readable one-line description of a workload."""
+    keys = ("q", "nx", "ny", "nz", "rho_h", "rho_l", "tau_h", "tau_l", "sigma", "xi", "mobility")
+    return ", ".join(f"{k}={cfg[k]:.6g}" if isinstance(cfg[k], float) else f"{k}={cfg[k]}"
+                     for k in keys if k in cfg)
+
+
+__all__ = ["drop2d", "rt3d", "rt_params", "jet3d", "jet_params", "jet_sweep", "sweep_lengths",
+           "sweep_weber", "perturb", "phi_in_profile", "summary"]
