@@ -28,9 +28,14 @@ def _grid(nx, ny, nz):
 
 
 def perturb(phi0, u0, seed, phi_amp=0.0, u_amp=0.0):
-    """Seeded noise added to initial fields (breaks exact symmetries in parity runs)."""
+    """Seeded noise added to initial fields (breaks exact symmetries in parity
+    runs).  The phase-field noise is weighted by 4 phi (1 - phi), so it lives
+    in the interfaces and leaves the bulk phases (and so rho >= rho_L) intact."""
     rng = np.random.default_rng(seed)
-    phi = phi0 + phi_amp * rng.standard_normal(phi0.shape) if phi_amp else phi0.copy()
+    if phi_amp:
+        phi = phi0 + phi_amp * 4.0 * phi0 * (1.0 - phi0) * rng.standard_normal(phi0.shape)
+    else:
+        phi = phi0.copy()
     if u_amp:
         un = u_amp * rng.standard_normal((3,) + phi0.shape)
         u = un if u0 is None else u0 + un
@@ -127,10 +132,12 @@ def jet_params(diameter, u_jet=0.02, rho_ratio=800.0, visc_ratio=50.0, reynolds=
                 xi=xi, mobility=mobility, g=g, u_jet=u_jet)
 
 
-def jet3d(nx=192, ny=192, nz=768, radius=12.0, stub=16.0, **kw):
+def jet3d(nx=192, ny=192, nz=768, radius=12.0, stub=16.0, param_radius=None, **kw):
     """Jet domain with the nozzle centred in the inlet face; the liquid column
-    initially fills z < stub inside the nozzle radius and moves at u_j."""
-    p = jet_params(2.0 * radius, **kw)
+    initially fills z < stub inside the nozzle radius and moves at u_j.
+    param_radius (default: radius) sets the nozzle radius the dimensionless
+    groups refer to, so that a small copy keeps the per-node parameters."""
+    p = jet_params(2.0 * (radius if param_radius is None else param_radius), **kw)
     cx, cy = nx / 2.0, ny / 2.0
     cfg = dict(q=19, nx=nx, ny=ny, nz=nz, rho_h=p["rho_h"], rho_l=p["rho_l"],
                tau_h=p["tau_h"], tau_l=p["tau_l"], sigma=p["sigma"], xi=p["xi"],

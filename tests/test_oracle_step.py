@@ -161,7 +161,7 @@ def test_streaming_matches_numpy(bc):
 
 def test_step_nodes_matches_full_step():
     """The sampled one-step evaluation equals the full-grid step at those nodes."""
-    cfg, phi0, u0 = W.jet3d(nx=12, ny=12, nz=16, radius=3.0, stub=5.0)
+    cfg, phi0, u0 = W.jet3d(nx=12, ny=12, nz=16, radius=3.0, param_radius=12.0, stub=5.0)
     phi, u = W.perturb(phi0, u0, 5, 0.01, 1e-3)
     o = oracle.Oracle(cfg).init(phi, u)
     o.step(3)
@@ -339,7 +339,7 @@ def test_uniform_plug_flow_through_inlet_and_outlet_is_fixed_point():
 def test_inlet_imposes_phi_and_velocity():
     """At every inlet node: sum h = phi_in (appendix B, mass condition) and
     sum e (g + F_a/2) = u_in (velocity condition)."""
-    cfg, phi0, u0 = W.jet3d(nx=16, ny=16, nz=20, radius=4.0, stub=6.0)
+    cfg, phi0, u0 = W.jet3d(nx=16, ny=16, nz=20, radius=4.0, param_radius=12.0, stub=6.0)
     phi, u = W.perturb(phi0, u0, 8, 0.01, 1e-3)
     o = oracle.Oracle(cfg).init(phi, u)
     o.step(15)
