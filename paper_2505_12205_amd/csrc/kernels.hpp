@@ -1,0 +1,838 @@
+// kernels.hpp -- gfx950 device code of the phase-field LBM step.
+//
+// One step at parity P (P = steps % 2) is
+//   k_phi<P>   : phi(x) = sum_a h_a(x)                      (Eq. phase_field_variable)
+//   k_step<P>  : stencil of phi, macroscopic update, both collisions and the
+//                in-place AA streaming of both population sets
+//   k_outlet<P>: convective outflow plane (only with an outlet face)
+//
+// Storage is structure-of-arrays, pop[a][node] with node = x + nx*(y + ny*z)
+// (x fastest), one array per set; streaming is the AA pattern:
+//   even step: read  pop[a][x],           write pop[abar][x]
+//   odd step : read  pop[abar][x - e_a],  write pop[a][x + e_a]
+// so every step reads and writes each population slot once, in place.  At
+// halfway walls the slot that the missing neighbour would have used is used
+// instead (bounce-back: pop[a][x]; specular reflection: the reflected slot of
+// the tangential neighbour), which keeps the read and write sets of each node
+// identical and the update race-free.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_FREESLIP = 2, BC_INLET = 3, BC_OUTLET = 4 };
+
+struct KParams {
+  int nx, ny, nz, N;       // grid, nodes
+  int plane;               // nodes of an inlet/outlet plane
+  float rho_l, drho;       // rho = rho_l + phi drho
+  float tau_l, dtau;       // tau = tau_l + phi dtau
+  float beta4, kappa;      // 4 beta, kappa of the chemical potential
+  float inv_xi, omega_h;   // 1/xi, 1/(tau_phi + 1/2)
+  float gx, gy, gz, fb_rhol;  // F_b = (rho - fb_rhol) g
+  int bc[6];
+  float in_c0, in_c1, in_R, in_u, two_over_xi;
+  int clamp;
+  int has_inlet, has_outlet;
+};
+
+struct KBufs {
+  void* h;                 // Q*N populations (storage type of the codec)
+  void* g;
+  float* u;                // 3*N, u[d*N + node]
+  const float* phi;        // phase field of this step (stencil)
+  float* phi_out;          // written by k_phi
+  const float* ref;        // phase field the stored populations were encoded with (16-bit forms)
+  float* obuf;             // outlet plane: h then g, (2Q) * plane
+};
+
+// ---------------------------------------------------------------------------
+// population codecs
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Codec;
+
+template <>
+struct Codec<0> {  // FP32 as is
+  using T = float;
+  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) { return p[i]; }
+  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) { p[i] = v; }
+  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return p[i]; }
+  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = v; }
+};
+
+template <>
+struct Codec<1> {  // FP16 deviations: h -> h/w - phi_src, g -> g/w
+  using T = _Float16;
+  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) {
+    return w * ((float)p[i] + ref);
+  }
+  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) {
+    p[i] = (T)(v * iw - ref);
+  }
+  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return w * (float)p[i]; }
+  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = (T)(v * iw); }
+};
+
+__device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
+  uint32_t b = __float_as_uint(v);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <>
+struct Codec<2> {  // BF16 deviations, same encoding as FP16
+  using T = uint16_t;
+  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) {
+    return w * (bf2f(p[i]) + ref);
+  }
+  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) {
+    p[i] = f2bf(v * iw - ref);
+  }
+  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return w * bf2f(p[i]); }
+  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = f2bf(v * iw); }
+};
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int node_of(const KParams& P, int x, int y, int z) {
+  return x + P.nx * (y + P.ny * z);
+}
+__device__ __forceinline__ int dim_of(const KParams& P, int d) { return d == 0 ? P.nx : (d == 1 ? P.ny : P.nz); }
+
+// Source of population a entering node c: the slot it is read from and the
+// node that produced it (for the 16-bit decode).  Returns false if the source
+// lies beyond the inlet or outlet face (the value then comes from that
+// boundary condition).
+template <int Q, int ODD>
+__device__ __forceinline__ bool resolve_src(const KParams& P, const int c[3], int a, int& slot_pop,
+                                            int& slot_node, int& src_node) {
+  int s[3];
+  int mask = 0;
+  bool noslip = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = ecomp<Q>(a, d);
+    s[d] = c[d] - e;
+    if (e == 0) continue;
+    const int n = dim_of(P, d);
+    if (s[d] < 0 || s[d] >= n) {
+      const int b = P.bc[2 * d + (s[d] >= n ? 1 : 0)];
+      if (b == BC_PERIODIC) {
+        s[d] = s[d] < 0 ? s[d] + n : s[d] - n;
+      } else if (b == BC_INLET || b == BC_OUTLET) {
+        return false;
+      } else {
+        mask |= 1 << d;
+        noslip |= (b == BC_NOSLIP);
+      }
+    }
+  }
+  if (mask == 0) {
+    src_node = node_of(P, s[0], s[1], s[2]);
+    slot_pop = ODD ? Lat<Q>::opp[a] : a;
+    slot_node = ODD ? src_node : node_of(P, c[0], c[1], c[2]);
+    return true;
+  }
+  const int self = node_of(P, c[0], c[1], c[2]);
+  if (noslip) {  // halfway bounce-back: post-collision abar of this node
+    src_node = self;
+    slot_pop = a;
+    slot_node = self;
+    return true;
+  }
+  // halfway specular reflection: post-collision reflect(a) of x - e_{a,t}
+  int t[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) t[d] = (mask >> d & 1) ? c[d] : s[d];
+  src_node = node_of(P, t[0], t[1], t[2]);
+  int r = a;
+  switch (mask) {  // constant-folded per a
+    case 1: r = reflect<Q>(a, 1); break;
+    case 2: r = reflect<Q>(a, 2); break;
+    case 3: r = reflect<Q>(a, 3); break;
+    case 4: r = reflect<Q>(a, 4); break;
+    case 5: r = reflect<Q>(a, 5); break;
+    case 6: r = reflect<Q>(a, 6); break;
+    default: r = reflect<Q>(a, 7); break;
+  }
+  slot_pop = ODD ? Lat<Q>::opp[r] : a;
+  slot_node = ODD ? src_node : self;
+  return true;
+}
+
+// Destination slot of post-collision population a leaving node c; false if it
+// leaves through the inlet or outlet face.
+template <int Q, int ODD>
+__device__ __forceinline__ bool resolve_dst(const KParams& P, const int c[3], int a, int& slot_pop,
+                                            int& slot_node) {
+  if (!ODD) {
+    slot_pop = Lat<Q>::opp[a];
+    slot_node = node_of(P, c[0], c[1], c[2]);
+    return true;
+  }
+  int t[3];
+  int mask = 0;
+  bool noslip = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = ecomp<Q>(a, d);
+    t[d] = c[d] + e;
+    if (e == 0) continue;
+    const int n = dim_of(P, d);
+    if (t[d] < 0 || t[d] >= n) {
+      const int b = P.bc[2 * d + (t[d] >= n ? 1 : 0)];
+      if (b == BC_PERIODIC) {
+        t[d] = t[d] < 0 ? t[d] + n : t[d] - n;
+      } else if (b == BC_INLET || b == BC_OUTLET) {
+        return false;
+      } else {
+        mask |= 1 << d;
+        noslip |= (b == BC_NOSLIP);
+      }
+    }
+  }
+  if (mask == 0) {
+    slot_pop = a;
+    slot_node = node_of(P, t[0], t[1], t[2]);
+    return true;
+  }
+  if (noslip) {
+    slot_pop = Lat<Q>::opp[a];
+    slot_node = node_of(P, c[0], c[1], c[2]);
+    return true;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (mask >> d & 1) t[d] = c[d];
+  int r = a;
+  switch (mask) {
+    case 1: r = reflect<Q>(a, 1); break;
+    case 2: r = reflect<Q>(a, 2); break;
+    case 3: r = reflect<Q>(a, 3); break;
+    case 4: r = reflect<Q>(a, 4); break;
+    case 5: r = reflect<Q>(a, 5); break;
+    case 6: r = reflect<Q>(a, 6); break;
+    default: r = reflect<Q>(a, 7); break;
+  }
+  slot_pop = r;
+  slot_node = node_of(P, t[0], t[1], t[2]);
+  return true;
+}
+
+// nozzle profile psi = 1/2 [1 + tanh(2 (R - r)/xi)] at tangential position (p0, p1)
+__device__ __forceinline__ float inlet_psi(const KParams& P, float p0, float p1) {
+  const float d0 = p0 - P.in_c0, d1 = p1 - P.in_c1;
+  const float r = sqrtf(d0 * d0 + d1 * d1);
+  return 0.5f * (1.0f + tanhf(P.two_over_xi * (P.in_R - r)));
+}
+
+// tangential coordinates of node c on the inlet face
+template <int Q>
+__device__ __forceinline__ void inlet_tangential(const int c[3], float& p0, float& p1) {
+  if (Lat<Q>::D == 3) {
+    p0 = (float)c[0];
+    p1 = (float)c[1];
+  } else {
+    p0 = (float)c[0];
+    p1 = 0.0f;
+  }
+}
+
+// phi at c + e_a with the ghost rules: periodic wrap; walls and outlet take
+// the adjacent fluid value; the inlet takes phi_in.
+template <int Q>
+__device__ __forceinline__ float phi_nb(const KParams& P, const float* __restrict__ phi, const int c[3],
+                                        int a) {
+  int t[3];
+  bool inlet = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = ecomp<Q>(a, d);
+    t[d] = c[d] + e;
+    if (e == 0) continue;
+    const int n = dim_of(P, d);
+    if (t[d] < 0 || t[d] >= n) {
+      const int b = P.bc[2 * d + (t[d] >= n ? 1 : 0)];
+      if (b == BC_PERIODIC) {
+        t[d] = t[d] < 0 ? t[d] + n : t[d] - n;
+      } else {
+        t[d] = t[d] < 0 ? 0 : n - 1;
+        inlet |= (b == BC_INLET);
+      }
+    }
+  }
+  if (inlet) {
+    float p0, p1;
+    inlet_tangential<Q>(t, p0, p1);
+    return inlet_psi(P, p0, p1);
+  }
+  return phi[node_of(P, t[0], t[1], t[2])];
+}
+
+template <int Q>
+__device__ __forceinline__ bool is_inlet_node(const KParams& P, const int c[3]) {
+  return P.has_inlet && c[Lat<Q>::AX] == 0;
+}
+template <int Q>
+__device__ __forceinline__ bool is_outlet_node(const KParams& P, const int c[3]) {
+  return P.has_outlet && c[Lat<Q>::AX] == dim_of(P, Lat<Q>::AX) - 1;
+}
+template <int Q>
+__device__ __forceinline__ int plane_index(const KParams& P, const int c[3]) {
+  return Lat<Q>::D == 3 ? c[0] + P.nx * c[1] : c[0];
+}
+
+// Velocity inlet (appendix B) at node c: fills the unknown populations
+// (e_a along the inward normal > 0) from the known ones, for both sets.
+template <int Q>
+__device__ __forceinline__ void apply_inlet(const KParams& P, const int c[3], float* h, float* g) {
+  constexpr int AX = Lat<Q>::AX;
+  float p0, p1;
+  inlet_tangential<Q>(c, p0, p1);
+  const float psi = inlet_psi(P, p0, p1);
+  const float un = P.in_u * psi;  // u_in along +AX
+  const float rho_in = P.rho_l + psi * P.drho;
+  const float fb = (rho_in - P.fb_rhol);
+  const float F[3] = {fb * P.gx, fb * P.gy, fb * P.gz};
+  const float inv_rho3 = 3.0f / rho_in;
+  float feq[Q], heq[Q], Fa[Q];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const float eu = ecomp<Q>(a, AX) * un;
+    const float w = Lat<Q>::w[a];
+    feq[a] = w * (3.0f * eu + 4.5f * eu * eu - 1.5f * un * un);
+    heq[a] = psi * w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * un * un);
+    Fa[a] = w * inv_rho3 * (ecomp<Q>(a, 0) * F[0] + ecomp<Q>(a, 1) * F[1] + ecomp<Q>(a, 2) * F[2]);
+  }
+  float M[3] = {0.f, 0.f, 0.f};
+  float theta = 0.f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if (ecomp<Q>(a, AX) != 0) continue;
+    const float fp = g[a] + 0.5f * Fa[a] - feq[a];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (ecomp<Q>(a, d) != 0) M[d] += ecomp<Q>(a, d) * fp;
+    theta += h[a] - heq[a];
+  }
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if (ecomp<Q>(a, AX) <= 0) continue;
+    const int b = Lat<Q>::opp[a];
+    const float eM = ecomp<Q>(a, 0) * M[0] + ecomp<Q>(a, 1) * M[1] + ecomp<Q>(a, 2) * M[2];
+    const float fpa = (g[b] + 0.5f * Fa[b]) + (feq[a] - feq[b]) - 0.5f * eM;
+    g[a] = fpa - 0.5f * Fa[a];
+    bool tang = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (d != AX && ecomp<Q>(a, d) != 0) tang = true;
+    h[a] = heq[a] - (h[b] - heq[b]) - (tang ? theta * (1.0f / Lat<Q>::NH) : 0.0f);
+  }
+}
+
+// Load the post-stream populations of node c for a step of parity ODD.
+template <int Q, int ST, int ODD, bool LOAD_G>
+__device__ __forceinline__ void load_node(const KParams& P, const KBufs& B, const int c[3], float* h,
+                                          float* g) {
+  using C = Codec<ST>;
+  using T = typename C::T;
+  const T* __restrict__ H = (const T*)B.h;
+  const T* __restrict__ G = (const T*)B.g;
+  const size_t N = (size_t)P.N;
+  if (is_outlet_node<Q>(P, c)) {
+    const int pi = plane_index<Q>(P, c);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      h[a] = B.obuf[(size_t)a * P.plane + pi];
+      if (LOAD_G) g[a] = B.obuf[(size_t)(Q + a) * P.plane + pi];
+    }
+    return;
+  }
+  const bool inlet = is_inlet_node<Q>(P, c);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    int sp, sn, src;
+    if (resolve_src<Q, ODD>(P, c, a, sp, sn, src)) {
+      const float ref = (ST == 0) ? 0.0f : B.ref[src];
+      h[a] = C::ld_h(H, (size_t)sp * N + sn, Lat<Q>::w[a], ref);
+      if (LOAD_G) g[a] = C::ld_g(G, (size_t)sp * N + sn, Lat<Q>::w[a]);
+    } else {
+      h[a] = 0.0f;
+      if (LOAD_G) g[a] = 0.0f;
+    }
+  }
+  if (inlet && LOAD_G) apply_inlet<Q>(P, c, h, g);
+}
+
+// XCD-aware tile order: consecutive hardware block ids go round-robin to the
+// 8 XCDs; remap so that each XCD walks a contiguous range of tiles (and its
+// L2 holds the phase-field planes its tiles share).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = b % 8, k = b / 8;
+  return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+struct Tiling {
+  int bx, by, ntx, nty, ntiles;
+};
+
+__device__ __forceinline__ bool tile_coords(const KParams& P, const Tiling& T, int c[3]) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = L % T.ntx;
+  const int r = L / T.ntx;
+  const int ty = r % T.nty;
+  c[2] = r / T.nty;
+  c[0] = tx * T.bx + (int)threadIdx.x % T.bx;
+  c[1] = ty * T.by + (int)threadIdx.x / T.bx;
+  return c[0] < P.nx && c[1] < P.ny;
+}
+
+// ---------------------------------------------------------------------------
+// k_phi: phase field of the current state
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T) {
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  float phi;
+  if (is_inlet_node<Q>(P, c)) {
+    float p0, p1;
+    inlet_tangential<Q>(c, p0, p1);
+    phi = inlet_psi(P, p0, p1);  // sum_a h_a = phi_in exactly after the inlet condition
+  } else {
+    float h[Q], g[1];
+    load_node<Q, ST, ODD, false>(P, B, c, h, g);
+    phi = 0.0f;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) phi += h[a];
+  }
+  B.phi_out[node] = phi;
+}
+
+// ---------------------------------------------------------------------------
+// node physics
+// ---------------------------------------------------------------------------
+struct Stress {  // second moments sum g e e
+  float xx, yy, zz, xy, yz, xz;
+};
+
+// Viscous force of the WMRT operator (Eq. viscous_force_wmrt) in the closed
+// form -tau [s dev(Pi) + tr(Pi)/d I] grad rho, Pi = sum e e (g - f^eq(p*, u)):
+// the weighted moment basis makes M^-1 S M act as s on the deviatoric
+// second moments and as 1 on their trace.
+template <int D>
+__device__ __forceinline__ void viscous_force(const Stress& S, float p, const float u[3], float tau,
+                                              float s, const float gr[3], float F[3]) {
+  const float p3 = p * (1.0f / 3.0f);
+  const float xx = S.xx - p3 - u[0] * u[0];
+  const float yy = S.yy - p3 - u[1] * u[1];
+  const float zz = (D == 3) ? S.zz - p3 - u[2] * u[2] : 0.0f;
+  const float xy = S.xy - u[0] * u[1];
+  const float yz = (D == 3) ? S.yz - u[1] * u[2] : 0.0f;
+  const float xz = (D == 3) ? S.xz - u[0] * u[2] : 0.0f;
+  const float tr = (xx + yy + zz) * (1.0f / D);
+  const float Txx = s * (xx - tr) + tr, Tyy = s * (yy - tr) + tr, Tzz = s * (zz - tr) + tr;
+  const float Txy = s * xy, Tyz = s * yz, Txz = s * xz;
+  F[0] = -tau * (Txx * gr[0] + Txy * gr[1] + Txz * gr[2]);
+  F[1] = -tau * (Txy * gr[0] + Tyy * gr[1] + Tyz * gr[2]);
+  F[2] = (D == 3) ? -tau * (Txz * gr[0] + Tyz * gr[1] + Tzz * gr[2]) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// k_step: fused macroscopic update + both collisions + AA streaming
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  using C = Codec<ST>;
+  using Ty = typename C::T;
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  const size_t N = (size_t)P.N;
+
+  // isotropic stencil of phi (Eqs. gradient_phi, laplacian_phi; c = dx = 1)
+  const float phi = B.phi[node];
+  float gr[3] = {0.f, 0.f, 0.f};
+  float lap = 0.f;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const float pn = phi_nb<Q>(P, B.phi, c, a);
+    const float w = L::w[a];
+    if (L::ex[a]) gr[0] += (w * L::ex[a]) * pn;
+    if (L::ey[a]) gr[1] += (w * L::ey[a]) * pn;
+    if (D == 3 && L::ez[a]) gr[2] += (w * L::ez[a]) * pn;
+    lap += w * (pn - phi);
+  }
+  gr[0] *= 3.0f;
+  gr[1] *= 3.0f;
+  gr[2] *= 3.0f;
+  lap *= 6.0f;
+
+  float h[Q], g[Q];
+  load_node<Q, ST, ODD, true>(P, B, c, h, g);
+
+  const float phc = P.clamp ? fminf(fmaxf(phi, 0.0f), 1.0f) : phi;
+  const float rho = P.rho_l + phc * P.drho;  // Eq. density_interpolation
+  const float inv_rho = 1.0f / rho;
+  // chemical potential with the bulk term 4 beta phi (phi-1)(phi-1/2)
+  const float mu = P.beta4 * phi * (phi - 1.0f) * (phi - 0.5f) - P.kappa * lap;
+  const float fb = rho - P.fb_rhol;
+  float Fsb[3], grho[3];
+  Fsb[0] = mu * gr[0] + fb * P.gx;  // surface tension + body force
+  Fsb[1] = mu * gr[1] + fb * P.gy;
+  Fsb[2] = mu * gr[2] + fb * P.gz;
+  grho[0] = P.drho * gr[0];  // Eq. density_gradient_phase_field
+  grho[1] = P.drho * gr[1];
+  grho[2] = P.drho * gr[2];
+
+  // moments of g
+  float p = 0.f, j[3] = {0.f, 0.f, 0.f};
+  Stress S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const float v = g[a];
+    p += v;
+    if (L::ex[a]) { j[0] += L::ex[a] * v; S.xx += v; }
+    if (L::ey[a]) { j[1] += L::ey[a] * v; S.yy += v; }
+    if (D == 3 && L::ez[a]) { j[2] += L::ez[a] * v; S.zz += v; }
+    if (L::ex[a] && L::ey[a]) S.xy += (L::ex[a] * L::ey[a]) * v;
+    if (D == 3 && L::ey[a] && L::ez[a]) S.yz += (L::ey[a] * L::ez[a]) * v;
+    if (D == 3 && L::ex[a] && L::ez[a]) S.xz += (L::ex[a] * L::ez[a]) * v;
+  }
+  const float tau = P.tau_l + phc * P.dtau;  // Eq. relaxation_time
+  const float s = 1.0f / (tau + 0.5f);
+
+  // macroscopic update: viscous force with the stored velocity
+  float up[3];
+  up[0] = B.u[node];
+  up[1] = B.u[N + node];
+  up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
+  float Fm[3];
+  viscous_force<D>(S, p, up, tau, s, grho, Fm);
+  const float p3 = p * (1.0f / 3.0f);
+  float u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float F = Fsb[d] - p3 * grho[d] + Fm[d];  // Eqs. total_force, pressure_force
+    u[d] = j[d] + 0.5f * F * inv_rho;               // Eq. velocity_update
+  }
+  if (D == 2) u[2] = 0.0f;
+  B.u[node] = u[0];
+  B.u[N + node] = u[1];
+  if (D == 3) B.u[2 * N + node] = u[2];
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+  // phase-field collision (Eqs. lbe_interface, forcing_term, equilibrium_with_force)
+  {
+    const float theta = (1.0f - 4.0f * (phi - 0.5f) * (phi - 0.5f)) * P.inv_xi;
+    const float nrm = rsqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + 1e-24f);
+    const float tn[3] = {theta * gr[0] * nrm, theta * gr[1] * nrm, theta * gr[2] * nrm};
+    const float om = P.omega_h;
+    Ty* __restrict__ H = (Ty*)B.h;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const float w = L::w[a];
+      const float eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
+      const float heq = phi * w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+      const float fphi = w * (L::ex[a] * tn[0] + L::ey[a] * tn[1] + L::ez[a] * tn[2]);
+      const float hp = h[a] - om * (h[a] - heq + 0.5f * fphi) + fphi;
+      int sp, sn;
+      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_h(H, (size_t)sp * N + sn, hp, 1.0f / w, phi);
+    }
+  }
+
+  // hydrodynamic collision: WMRT with the viscous force re-evaluated at u^n
+  {
+    float Fc[3];
+    viscous_force<D>(S, p, u, tau, s, grho, Fc);
+    float F[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] = Fsb[d] - p3 * grho[d] + Fc[d];
+    // deviatoric second moments of g - fbar: dev(S - u u)
+    const float dxx = S.xx - u[0] * u[0], dyy = S.yy - u[1] * u[1];
+    const float dzz = (D == 3) ? S.zz - u[2] * u[2] : 0.0f;
+    const float dxy = S.xy - u[0] * u[1];
+    const float dyz = (D == 3) ? S.yz - u[1] * u[2] : 0.0f;
+    const float dxz = (D == 3) ? S.xz - u[0] * u[2] : 0.0f;
+    const float one_s = 1.0f - s;
+    const float f3r = 3.0f * inv_rho;
+    Ty* __restrict__ G = (Ty*)B.g;
+    float cxx, cyy, czz, cxy, cyz, cxz;  // projection coefficients times (1 - s)
+    if (D == 3) {
+      // weighted basis: P y = 4.5 w_a (e e : dev)
+      const float tr = (dxx + dyy + dzz) * (1.0f / 3.0f);
+      cxx = 4.5f * one_s * (dxx - tr);
+      cyy = 4.5f * one_s * (dyy - tr);
+      czz = 4.5f * one_s * (dzz - tr);
+      cxy = 9.0f * one_s * dxy;
+      cyz = 9.0f * one_s * dyz;
+      cxz = 9.0f * one_s * dxz;
+    } else {
+      // plain orthogonal D2Q9 basis: P y = [(ex^2-ey^2)(dxx-dyy) + ex ey dxy] / 4
+      cxx = 0.25f * one_s * (dxx - dyy);
+      cyy = -cxx;
+      czz = 0.0f;
+      cxy = 0.25f * one_s * dxy;
+      cyz = cxz = 0.0f;
+    }
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
+      const float w = L::w[a];
+      const float eu = ex * u[0] + ey * u[1] + ez * u[2];
+      const float feq = w * (p + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+      const float Fa = w * f3r * (ex * F[0] + ey * F[1] + ez * F[2]);
+      float proj = 0.0f;
+      if (ex) proj += cxx;
+      if (ey) proj += cyy;
+      if (ez) proj += czz;
+      if (ex && ey) proj += (ex * ey) * cxy;
+      if (ey && ez) proj += (ey * ez) * cyz;
+      if (ex && ez) proj += (ex * ez) * cxz;
+      if (D == 3) proj *= w;
+      const float gp = feq + 0.5f * Fa + proj;
+      int sp, sn;
+      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_g(G, (size_t)sp * N + sn, gp, 1.0f / w);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_outlet: convective outflow (appendix B) after the step of parity ODD
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
+  constexpr int AX = Lat<Q>::AX;
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= P.plane) return;
+  int c[3];
+  if (Lat<Q>::D == 3) {
+    c[0] = pi % P.nx;
+    c[1] = pi / P.nx;
+    c[2] = P.nz - 2;
+  } else {
+    c[0] = pi;
+    c[1] = P.ny - 2;
+    c[2] = 0;
+  }
+  // populations streamed into the layer N-1 (read as the next step will)
+  float h[Q], g[Q];
+  load_node<Q, ST, !ODD, true>(P, B, c, h, g);
+  const int node = node_of(P, c[0], c[1], c[2]);
+  const float U = fmaxf(B.u[(size_t)AX * P.N + node], 0.0f);
+  const float inv = 1.0f / (1.0f + U);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    float* oh = B.obuf + (size_t)a * P.plane + pi;
+    float* og = B.obuf + (size_t)(Q + a) * P.plane + pi;
+    *oh = (*oh + U * h[a]) * inv;
+    *og = (*og + U * g[a]) * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initial state, export, import, fields, reductions
+// ---------------------------------------------------------------------------
+
+// canonical (even-parity) initial populations from phi0, u0; the 16-bit
+// reference is phi0.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_init(KParams P, KBufs B, const float* __restrict__ phi0,
+                                              const float* __restrict__ u0, Tiling T) {
+  using L = Lat<Q>;
+  using C = Codec<ST>;
+  using Ty = typename C::T;
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  const size_t N = (size_t)P.N;
+  const float phi = phi0[node];
+  float gr[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const float pn = phi_nb<Q>(P, phi0, c, a);
+    gr[0] += (L::w[a] * L::ex[a]) * pn;
+    gr[1] += (L::w[a] * L::ey[a]) * pn;
+    gr[2] += (L::w[a] * L::ez[a]) * pn;
+  }
+  gr[0] *= 3.0f;
+  gr[1] *= 3.0f;
+  gr[2] *= 3.0f;
+  float u[3] = {0.f, 0.f, 0.f};
+  if (u0) {
+    u[0] = u0[node];
+    u[1] = u0[N + node];
+    u[2] = (L::D == 3) ? u0[2 * N + node] : 0.0f;
+  }
+  B.u[node] = u[0];
+  B.u[N + node] = u[1];
+  B.u[2 * N + node] = u[2];
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float theta = (1.0f - 4.0f * (phi - 0.5f) * (phi - 0.5f)) * P.inv_xi;
+  const float nrm = rsqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + 1e-24f);
+  const bool outlet = is_outlet_node<Q>(P, c);
+  const int pi = plane_index<Q>(P, c);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const float w = L::w[a];
+    const float eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
+    const float G1 = 1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu;
+    const float fphi = theta * w * (L::ex[a] * gr[0] + L::ey[a] * gr[1] + L::ez[a] * gr[2]) * nrm;
+    const float hv = phi * w * G1 - 0.5f * fphi;
+    const float gv = w * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+    if (outlet) {
+      B.obuf[(size_t)a * P.plane + pi] = hv;
+      B.obuf[(size_t)(Q + a) * P.plane + pi] = gv;
+    }
+    int sp, sn, src;
+    if (resolve_src<Q, 0>(P, c, a, sp, sn, src)) {
+      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : phi0[src]);
+      C::st_g((Ty*)B.g, (size_t)sp * N + sn, gv, 1.0f / w);
+    }
+  }
+}
+
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void k_export(KParams P, KBufs B, float* __restrict__ ho,
+                                                float* __restrict__ go, float* __restrict__ uo, Tiling T) {
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  const size_t N = (size_t)P.N;
+  float h[Q], g[Q];
+  load_node<Q, ST, ODD, true>(P, B, c, h, g);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    if (ho) ho[(size_t)a * N + node] = h[a];
+    if (go) go[(size_t)a * N + node] = g[a];
+  }
+  if (uo)
+    for (int d = 0; d < 3; ++d) uo[(size_t)d * N + node] = B.u[(size_t)d * N + node];
+}
+
+// import, pass 1: reference phase field sum_a h_a of the canonical input
+template <int Q>
+__global__ __launch_bounds__(256) void k_import_ref(KParams P, const float* __restrict__ hi,
+                                                    float* __restrict__ ref, Tiling T) {
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  float s = 0.f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) s += hi[(size_t)a * P.N + node];
+  ref[node] = s;
+}
+
+// import, pass 2: store canonical populations in even-parity slots
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_import(KParams P, KBufs B, const float* __restrict__ hi,
+                                                const float* __restrict__ gi, const float* __restrict__ ui,
+                                                Tiling T) {
+  using C = Codec<ST>;
+  using Ty = typename C::T;
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  const size_t N = (size_t)P.N;
+  const bool outlet = is_outlet_node<Q>(P, c);
+  const int pi = plane_index<Q>(P, c);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const float hv = hi[(size_t)a * N + node], gv = gi[(size_t)a * N + node];
+    if (outlet) {
+      B.obuf[(size_t)a * P.plane + pi] = hv;
+      B.obuf[(size_t)(Q + a) * P.plane + pi] = gv;
+    }
+    int sp, sn, src;
+    if (resolve_src<Q, 0>(P, c, a, sp, sn, src)) {
+      const float w = Lat<Q>::w[a];
+      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : B.ref[src]);
+      C::st_g((Ty*)B.g, (size_t)sp * N + sn, gv, 1.0f / w);
+    }
+  }
+  for (int d = 0; d < 3; ++d) B.u[(size_t)d * N + node] = ui[(size_t)d * N + node];
+}
+
+// p = p* rho cs^2 of the current state (phi from the current phase field)
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void k_pressure(KParams P, KBufs B, float* __restrict__ po, Tiling T) {
+  int c[3];
+  if (!tile_coords(P, T, c)) return;
+  const int node = node_of(P, c[0], c[1], c[2]);
+  float h[Q], g[Q];
+  load_node<Q, ST, ODD, true>(P, B, c, h, g);
+  float ps = 0.f, ph = 0.f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    ps += g[a];
+    ph += h[a];
+  }
+  const float phc = P.clamp ? fminf(fmaxf(ph, 0.0f), 1.0f) : ph;
+  po[node] = ps * (P.rho_l + phc * P.drho) * (1.0f / 3.0f);
+}
+
+// FP64 sums of phi and 0.5 rho |u|^2: per-block partials in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_partial(KParams P, const float* __restrict__ phi,
+                                                        const float* __restrict__ u, double* __restrict__ part) {
+  __shared__ double sm[256], sk[256];
+  double m = 0.0, k = 0.0;
+  const size_t N = (size_t)P.N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+    const double ph = phi[i];
+    const double phc = P.clamp ? fmin(fmax(ph, 0.0), 1.0) : ph;
+    const double rho = (double)P.rho_l + phc * (double)P.drho;
+    const double ux = u[i], uy = u[N + i], uz = u[2 * N + i];
+    m += ph;
+    k += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+  }
+  sm[threadIdx.x] = m;
+  sk[threadIdx.x] = k;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[threadIdx.x] += sm[threadIdx.x + o];
+      sk[threadIdx.x] += sk[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sm[0];
+    part[2 * blockIdx.x + 1] = sk[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nparts,
+                                                      double* __restrict__ out) {
+  __shared__ double sm[256], sk[256];
+  double m = 0.0, k = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    m += part[2 * i];
+    k += part[2 * i + 1];
+  }
+  sm[threadIdx.x] = m;
+  sk[threadIdx.x] = k;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[threadIdx.x] += sm[threadIdx.x + o];
+      sk[threadIdx.x] += sk[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sm[0];
+    out[1] = sk[0];
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,612 @@
+// lbm.hip -- host runtime and C ABI (include/lbm.h) of the gfx950
+// phase-field lattice Boltzmann library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t h, g, u, phi0, phi1, obuf, total;
+};
+
+int pop_size(int storage) { return storage == LBM_FP32 ? 4 : 2; }
+
+int axis_of(int lattice) { return lattice == LBM_D2Q9 ? 1 : 2; }
+
+int plane_of(const lbm_params& p) { return p.lattice == LBM_D2Q9 ? p.nx : p.nx * p.ny; }
+
+bool has_outlet(const lbm_params& p) {
+  for (int f = 0; f < 6; ++f)
+    if (p.bc[f] == LBM_BC_CONVECTIVE_OUTLET) return true;
+  return false;
+}
+bool has_inlet(const lbm_params& p) {
+  for (int f = 0; f < 6; ++f)
+    if (p.bc[f] == LBM_BC_VELOCITY_INLET) return true;
+  return false;
+}
+
+int validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "null parameters");
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "lattice must be 9 or 19");
+  if (p->nx < 2 || p->ny < 2 || p->nz < 1) return fail(LBM_EINVAL, "grid too small");
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz = 1");
+  if (p->lattice == LBM_D3Q19 && p->nz < 2) return fail(LBM_EINVAL, "D3Q19 needs nz >= 2");
+  const double nodes = (double)p->nx * p->ny * p->nz;
+  if (nodes * 19 >= 2147483647.0 * 4) return fail(LBM_EINVAL, "grid too large for one domain");
+  if (nodes >= 2147483647.0) return fail(LBM_EINVAL, "grid too large for one domain");
+  if (!(p->tau_h > -0.5) || !(p->tau_l > -0.5)) return fail(LBM_EINVAL, "tau must exceed -1/2");
+  if (!(p->xi > 0.0)) return fail(LBM_EINVAL, "xi must be positive");
+  if (!(p->rho_l > 0.0) || !(p->rho_h > 0.0)) return fail(LBM_EINVAL, "densities must be positive");
+  if (!(p->mobility >= 0.0)) return fail(LBM_EINVAL, "mobility must be non-negative");
+  if (p->storage < LBM_FP32 || p->storage > LBM_BF16_DEV) return fail(LBM_EINVAL, "unknown storage");
+  if (p->body_force != LBM_FB_RHO_G && p->body_force != LBM_FB_RHO_MINUS_RHOL_G)
+    return fail(LBM_EINVAL, "unknown body force");
+  const int ndim = p->lattice == LBM_D2Q9 ? 2 : 3;
+  const int ax = axis_of(p->lattice);
+  for (int d = 0; d < 3; ++d) {
+    const int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
+    if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return fail(LBM_EINVAL, "unknown boundary type");
+    if (d >= ndim) {
+      if (lo != LBM_BC_PERIODIC || hi != LBM_BC_PERIODIC)
+        return fail(LBM_EINVAL, "faces of the z axis must be periodic in 2D");
+      continue;
+    }
+    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC))
+      return fail(LBM_EINVAL, "periodic faces must be paired");
+    if (lo == LBM_BC_CONVECTIVE_OUTLET || hi == LBM_BC_VELOCITY_INLET)
+      return fail(LBM_EUNSUPPORTED, "inlet only on the minus face, outlet only on the plus face");
+    if ((lo == LBM_BC_VELOCITY_INLET || hi == LBM_BC_CONVECTIVE_OUTLET) && d != ax)
+      return fail(LBM_EUNSUPPORTED, "inlet/outlet only on the last axis (z in 3D, y in 2D)");
+  }
+  if (has_outlet(*p)) {
+    const int n = ax == 2 ? p->nz : p->ny;
+    if (n < 3) return fail(LBM_EINVAL, "outlet axis needs at least 3 nodes");
+    if (p->outlet_mode != LBM_OUTLET_LOCAL)
+      return fail(LBM_EUNSUPPORTED, "only the local convective velocity is implemented");
+  }
+  return LBM_OK;
+}
+
+Layout layout_of(const lbm_params& p) {
+  const size_t Q = (size_t)p.lattice;
+  const size_t N = (size_t)p.nx * p.ny * p.nz;
+  const size_t ps = (size_t)pop_size(p.storage);
+  Layout L;
+  size_t off = 0;
+  L.h = off;
+  off = align256(off + Q * N * ps);
+  L.g = off;
+  off = align256(off + Q * N * ps);
+  L.u = off;
+  off = align256(off + 3 * N * 4);
+  L.phi0 = off;
+  off = align256(off + N * 4);
+  L.phi1 = off;
+  if (p.storage != LBM_FP32) off = align256(off + N * 4);
+  L.obuf = off;
+  if (has_outlet(p)) off = align256(off + 2 * Q * (size_t)plane_of(p) * 4);
+  L.total = off;
+  return L;
+}
+
+KParams kparams_of(const lbm_params& p) {
+  KParams K;
+  memset(&K, 0, sizeof K);
+  K.nx = p.nx;
+  K.ny = p.ny;
+  K.nz = p.nz;
+  K.N = p.nx * p.ny * p.nz;
+  K.plane = plane_of(p);
+  K.rho_l = (float)p.rho_l;
+  K.drho = (float)(p.rho_h - p.rho_l);
+  K.tau_l = (float)p.tau_l;
+  K.dtau = (float)(p.tau_h - p.tau_l);
+  const double beta = 12.0 * p.sigma / p.xi, kappa = 1.5 * p.sigma * p.xi;  // Eq. beta_kappa_relation
+  K.beta4 = (float)(4.0 * beta);
+  K.kappa = (float)kappa;
+  K.inv_xi = (float)(1.0 / p.xi);
+  K.omega_h = (float)(1.0 / (3.0 * p.mobility + 0.5));  // tau_phi = M / cs^2
+  K.gx = (float)p.gravity[0];
+  K.gy = (float)p.gravity[1];
+  K.gz = (float)p.gravity[2];
+  K.fb_rhol = p.body_force == LBM_FB_RHO_MINUS_RHOL_G ? (float)p.rho_l : 0.0f;
+  for (int f = 0; f < 6; ++f) K.bc[f] = p.bc[f];
+  K.in_c0 = (float)p.inlet_center[0];
+  K.in_c1 = (float)p.inlet_center[1];
+  K.in_R = (float)p.inlet_radius;
+  K.in_u = (float)p.inlet_u;
+  K.two_over_xi = (float)(2.0 / p.xi);
+  K.clamp = (p.variant_flags & LBM_VF_CLAMP_PHI) ? 1 : 0;
+  K.has_inlet = has_inlet(p) ? 1 : 0;
+  K.has_outlet = has_outlet(p) ? 1 : 0;
+  return K;
+}
+
+Tiling tiling_of(const lbm_params& p, int bx, int by) {
+  Tiling T;
+  T.bx = bx;
+  T.by = by;
+  T.ntx = (p.nx + bx - 1) / bx;
+  T.nty = (p.ny + by - 1) / by;
+  T.ntiles = T.ntx * T.nty * p.nz;
+  return T;
+}
+
+void default_tile(const lbm_params& p, int& bx, int& by) {
+  if (p.nx >= 64 && p.nx % 64 == 0) {
+    bx = 64;
+    by = 4;
+  } else if (p.nx % 32 == 0) {
+    bx = 32;
+    by = 8;
+  } else {
+    bx = 64;
+    by = 4;
+  }
+}
+
+}  // namespace
+
+struct lbm_sim {
+  lbm_params P;
+  KParams K;
+  Tiling T;
+  Layout L;
+  int Q, ST;
+  size_t N;
+  char* base;
+  hipStream_t stream;   // caller's stream (all launches)
+  hipStream_t cap;      // private stream used only to capture graphs
+  long long steps;
+  double* part;         // reduction partials (library scratch)
+  double* res;          // 2 doubles on the device
+  double* res_host;     // pinned
+  int nparts;
+  hipGraphExec_t g_pair, g_many;
+  int many_pairs;
+  bool graphs_ok;
+  float* phi(int i) { return (float*)(base + (i == 0 ? L.phi0 : L.phi1)); }
+  void* h() { return base + L.h; }
+  void* g() { return base + L.g; }
+  float* u() { return (float*)(base + L.u); }
+  float* obuf() { return has_outlet(P) ? (float*)(base + L.obuf) : nullptr; }
+  int parity() const { return (int)(steps & 1); }
+  // 16-bit forms ping-pong two phase-field buffers: at parity p the stored
+  // populations were encoded with phi[p] and this step's phi goes to phi[1-p].
+  float* ref_buf(int par) { return ST == LBM_FP32 ? phi(0) : phi(par); }
+  float* out_buf(int par) { return ST == LBM_FP32 ? phi(0) : phi(1 - par); }
+  KBufs bufs(int par) {
+    KBufs B;
+    B.h = h();
+    B.g = g();
+    B.u = u();
+    B.phi = out_buf(par);
+    B.phi_out = out_buf(par);
+    B.ref = ref_buf(par);
+    B.obuf = obuf();
+    return B;
+  }
+};
+
+namespace {
+
+// ---- template dispatch ----------------------------------------------------
+template <int Q, int ST>
+hipError_t launch_step_t(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
+  const KParams& K = s->K;
+  const Tiling& T = s->T;
+  const dim3 grid(T.ntiles), block(T.bx * T.by);
+  KBufs B = s->bufs(par);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  if (par == 0)
+    hipLaunchKernelGGL((k_phi<Q, ST, 0>), grid, block, 0, st, K, B, T);
+  else
+    hipLaunchKernelGGL((k_phi<Q, ST, 1>), grid, block, 0, st, K, B, T);
+  if (ev) (void)hipEventRecord(ev[1], st);
+  if (par == 0)
+    hipLaunchKernelGGL((k_step<Q, ST, 0>), grid, block, 0, st, K, B, T);
+  else
+    hipLaunchKernelGGL((k_step<Q, ST, 1>), grid, block, 0, st, K, B, T);
+  if (ev) (void)hipEventRecord(ev[2], st);
+  if (K.has_outlet) {
+    KBufs Bo = B;
+    Bo.ref = s->out_buf(par);
+    const dim3 pg((K.plane + 255) / 256), pb(256);
+    if (par == 0)
+      hipLaunchKernelGGL((k_outlet<Q, ST, 0>), pg, pb, 0, st, K, Bo);
+    else
+      hipLaunchKernelGGL((k_outlet<Q, ST, 1>), pg, pb, 0, st, K, Bo);
+  }
+  if (ev) (void)hipEventRecord(ev[3], st);
+  return hipGetLastError();
+}
+
+template <int Q>
+hipError_t launch_step_q(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
+  switch (s->ST) {
+    case LBM_FP32: return launch_step_t<Q, 0>(s, par, st, ev);
+    case LBM_FP16_DEV: return launch_step_t<Q, 1>(s, par, st, ev);
+    default: return launch_step_t<Q, 2>(s, par, st, ev);
+  }
+}
+
+hipError_t launch_step(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev = nullptr) {
+  return s->Q == 9 ? launch_step_q<9>(s, par, st, ev) : launch_step_q<19>(s, par, st, ev);
+}
+
+template <int Q, int ST>
+hipError_t launch_phi_t(lbm_sim* s, hipStream_t st) {
+  const int par = s->parity();
+  KBufs B = s->bufs(par);
+  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
+  if (par == 0)
+    hipLaunchKernelGGL((k_phi<Q, ST, 0>), grid, block, 0, st, s->K, B, s->T);
+  else
+    hipLaunchKernelGGL((k_phi<Q, ST, 1>), grid, block, 0, st, s->K, B, s->T);
+  return hipGetLastError();
+}
+
+template <int Q>
+hipError_t launch_phi_q(lbm_sim* s, hipStream_t st) {
+  switch (s->ST) {
+    case LBM_FP32: return launch_phi_t<Q, 0>(s, st);
+    case LBM_FP16_DEV: return launch_phi_t<Q, 1>(s, st);
+    default: return launch_phi_t<Q, 2>(s, st);
+  }
+}
+
+hipError_t launch_phi(lbm_sim* s) {
+  return s->Q == 9 ? launch_phi_q<9>(s, s->stream) : launch_phi_q<19>(s, s->stream);
+}
+
+template <int Q, int ST>
+hipError_t launch_init_t(lbm_sim* s, const float* phi0, const float* u0) {
+  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
+  KBufs B = s->bufs(0);
+  hipLaunchKernelGGL((k_init<Q, ST>), grid, block, 0, s->stream, s->K, B, phi0, u0, s->T);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+hipError_t launch_export_t(lbm_sim* s, float* ho, float* go, float* uo) {
+  const int par = s->parity();
+  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
+  KBufs B = s->bufs(par);
+  if (par == 0)
+    hipLaunchKernelGGL((k_export<Q, ST, 0>), grid, block, 0, s->stream, s->K, B, ho, go, uo, s->T);
+  else
+    hipLaunchKernelGGL((k_export<Q, ST, 1>), grid, block, 0, s->stream, s->K, B, ho, go, uo, s->T);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+hipError_t launch_import_t(lbm_sim* s, const float* hi, const float* gi, const float* ui) {
+  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
+  KBufs B = s->bufs(0);
+  hipLaunchKernelGGL((k_import_ref<Q>), grid, block, 0, s->stream, s->K, hi, s->ref_buf(0), s->T);
+  hipLaunchKernelGGL((k_import<Q, ST>), grid, block, 0, s->stream, s->K, B, hi, gi, ui, s->T);
+  return hipGetLastError();
+}
+
+template <int Q, int ST>
+hipError_t launch_pressure_t(lbm_sim* s, float* po) {
+  const int par = s->parity();
+  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
+  KBufs B = s->bufs(par);
+  if (par == 0)
+    hipLaunchKernelGGL((k_pressure<Q, ST, 0>), grid, block, 0, s->stream, s->K, B, po, s->T);
+  else
+    hipLaunchKernelGGL((k_pressure<Q, ST, 1>), grid, block, 0, s->stream, s->K, B, po, s->T);
+  return hipGetLastError();
+}
+
+#define DISPATCH(fn, s, ...)                                                          \
+  ((s)->Q == 9 ? ((s)->ST == 0   ? fn<9, 0>((s), __VA_ARGS__)                          \
+                  : (s)->ST == 1 ? fn<9, 1>((s), __VA_ARGS__)                          \
+                                 : fn<9, 2>((s), __VA_ARGS__))                         \
+               : ((s)->ST == 0   ? fn<19, 0>((s), __VA_ARGS__)                         \
+                  : (s)->ST == 1 ? fn<19, 1>((s), __VA_ARGS__)                         \
+                                 : fn<19, 2>((s), __VA_ARGS__)))
+
+void drop_graphs(lbm_sim* s) {
+  if (s->g_pair) hipGraphExecDestroy(s->g_pair);
+  if (s->g_many) hipGraphExecDestroy(s->g_many);
+  s->g_pair = s->g_many = nullptr;
+  s->graphs_ok = false;
+}
+
+int capture(lbm_sim* s, int pairs, hipGraphExec_t* out) {
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < pairs && err == hipSuccess; ++i) {
+    err = launch_step(s, 0, s->cap);
+    if (err == hipSuccess) err = launch_step(s, 1, s->cap);
+  }
+  hipError_t e2 = hipStreamEndCapture(s->cap, &graph);
+  if (err != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(err));
+  }
+  if (e2 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
+  hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
+  return LBM_OK;
+}
+
+int build_graphs(lbm_sim* s) {
+  drop_graphs(s);
+  // about 4M node updates per pair of steps or more per graph launch
+  s->many_pairs = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)4000000 / std::max<size_t>(1, s->N)));
+  int rc = capture(s, 1, &s->g_pair);
+  if (rc) return rc;
+  if (s->many_pairs > 1) {
+    rc = capture(s, s->many_pairs, &s->g_many);
+    if (rc) return rc;
+  }
+  s->graphs_ok = true;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_version(void) { return "lbm-pf-gfx950 0.1"; }
+
+int lbm_state_bytes(const lbm_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "null output");
+  *bytes = layout_of(*p).total;
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, void* state_dev,
+             size_t state_bytes, void* stream, lbm_sim** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out || !phi0_dev || !state_dev) return fail(LBM_EINVAL, "null pointer argument");
+  const Layout L = layout_of(*p);
+  if (state_bytes < L.total) return fail(LBM_ENOMEM, "state buffer smaller than lbm_state_bytes()");
+  if (((uintptr_t)state_dev) & 255) return fail(LBM_EINVAL, "state buffer must be 256-byte aligned");
+  lbm_sim* s = new lbm_sim();
+  s->P = *p;
+  s->K = kparams_of(*p);
+  s->L = L;
+  s->Q = p->lattice;
+  s->ST = p->storage;
+  s->N = (size_t)p->nx * p->ny * p->nz;
+  s->base = (char*)state_dev;
+  s->stream = (hipStream_t)stream;
+  s->steps = 0;
+  s->g_pair = s->g_many = nullptr;
+  s->graphs_ok = false;
+  int bx, by;
+  default_tile(*p, bx, by);
+  s->T = tiling_of(*p, bx, by);
+  s->nparts = 1024;
+  hipError_t e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&s->part, sizeof(double) * 2 * s->nparts);
+  if (e == hipSuccess) e = hipMalloc(&s->res, sizeof(double) * 2);
+  if (e == hipSuccess) e = hipHostMalloc(&s->res_host, sizeof(double) * 2, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(LBM_ENOMEM, std::string("library scratch: ") + hipGetErrorString(e));
+  }
+  e = DISPATCH(launch_init_t, s, phi0_dev, u0_dev);
+  if (e != hipSuccess) {
+    lbm_destroy(s);
+    return fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
+  }
+  // the 16-bit forms decode with the phase field of the encoding step: phi0
+  if (s->ST != LBM_FP32) {
+    e = hipMemcpyAsync(s->ref_buf(0), phi0_dev, s->N * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) {
+      lbm_destroy(s);
+      return fail(LBM_EDEVICE, std::string("init copy: ") + hipGetErrorString(e));
+    }
+  }
+  *out = s;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_sim* s, int n) {
+  if (!s || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
+  if (n >= 2 && !s->graphs_ok) {
+    int rc = build_graphs(s);
+    if (rc) return rc;
+  }
+  while (n > 0) {
+    if (s->parity() == 1 || n == 1) {
+      HIPCHK(launch_step(s, s->parity(), s->stream));
+      s->steps += 1;
+      n -= 1;
+    } else if (s->g_many && n >= 2 * s->many_pairs) {
+      HIPCHK(hipGraphLaunch(s->g_many, s->stream));
+      s->steps += 2 * s->many_pairs;
+      n -= 2 * s->many_pairs;
+    } else {
+      HIPCHK(hipGraphLaunch(s->g_pair, s->stream));
+      s->steps += 2;
+      n -= 2;
+    }
+  }
+  return LBM_OK;
+}
+
+long long lbm_steps_done(const lbm_sim* s) { return s ? s->steps : -1; }
+
+int lbm_fields(lbm_sim* s, unsigned mask, float* phi_dev, float* u_dev, float* p_dev) {
+  if (!s) return fail(LBM_EINVAL, "null handle");
+  if ((mask & LBM_FIELD_PHI) && !phi_dev) return fail(LBM_EINVAL, "null phi buffer");
+  if ((mask & LBM_FIELD_U) && !u_dev) return fail(LBM_EINVAL, "null u buffer");
+  if ((mask & LBM_FIELD_P) && !p_dev) return fail(LBM_EINVAL, "null p buffer");
+  if (mask & LBM_FIELD_PHI) {
+    HIPCHK(launch_phi(s));
+    HIPCHK(hipMemcpyAsync(phi_dev, s->out_buf(s->parity()), s->N * sizeof(float), hipMemcpyDeviceToDevice,
+                          s->stream));
+  }
+  if (mask & LBM_FIELD_U)
+    HIPCHK(hipMemcpyAsync(u_dev, s->u(), 3 * s->N * sizeof(float), hipMemcpyDeviceToDevice, s->stream));
+  if (mask & LBM_FIELD_P) HIPCHK(DISPATCH(launch_pressure_t, s, p_dev));
+  return LBM_OK;
+}
+
+int lbm_reduce(lbm_sim* s, double* mass, double* kinetic) {
+  if (!s || !mass || !kinetic) return fail(LBM_EINVAL, "null argument");
+  HIPCHK(launch_phi(s));
+  hipLaunchKernelGGL(k_reduce_partial, dim3(s->nparts), dim3(256), 0, s->stream, s->K,
+                     (const float*)s->out_buf(s->parity()), (const float*)s->u(), s->part);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s->stream, (const double*)s->part, s->nparts,
+                     s->res);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(s->res_host, s->res, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  *mass = s->res_host[0];
+  *kinetic = s->res_host[1];
+  if (!std::isfinite(*mass) || !std::isfinite(*kinetic))
+    return fail(LBM_EUNSTABLE, "non-finite mass or kinetic energy");
+  return LBM_OK;
+}
+
+int lbm_export_state(lbm_sim* s, float* h_dev, float* g_dev, float* u_dev) {
+  if (!s) return fail(LBM_EINVAL, "null handle");
+  HIPCHK(DISPATCH(launch_export_t, s, h_dev, g_dev, u_dev));
+  return LBM_OK;
+}
+
+int lbm_import_state(lbm_sim* s, const float* h_dev, const float* g_dev, const float* u_dev) {
+  if (!s || !h_dev || !g_dev || !u_dev) return fail(LBM_EINVAL, "null argument");
+  s->steps = 0;  // canonical state is stored in even-parity slots
+  HIPCHK(DISPATCH(launch_import_t, s, h_dev, g_dev, u_dev));
+  return LBM_OK;
+}
+
+int lbm_checkpoint_bytes(const lbm_sim* s, size_t* bytes) {
+  if (!s || !bytes) return fail(LBM_EINVAL, "null argument");
+  *bytes = s->L.total + 64;
+  return LBM_OK;
+}
+
+int lbm_save(lbm_sim* s, void* host_buf, size_t bytes) {
+  if (!s || !host_buf || bytes < s->L.total + 64) return fail(LBM_EINVAL, "bad checkpoint buffer");
+  char* hb = (char*)host_buf;
+  memset(hb, 0, 64);
+  memcpy(hb, "LBMPF001", 8);
+  memcpy(hb + 8, &s->steps, sizeof(long long));
+  memcpy(hb + 16, &s->L.total, sizeof(size_t));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(hb + 64, s->base, s->L.total, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes) {
+  if (!s || !host_buf || bytes < s->L.total + 64) return fail(LBM_EINVAL, "bad checkpoint buffer");
+  const char* hb = (const char*)host_buf;
+  size_t tot = 0;
+  memcpy(&tot, hb + 16, sizeof(size_t));
+  if (memcmp(hb, "LBMPF001", 8) != 0 || tot != s->L.total)
+    return fail(LBM_EINVAL, "checkpoint does not match this simulation");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpy(s->base, hb + 64, s->L.total, hipMemcpyHostToDevice));
+  memcpy(&s->steps, hb + 8, sizeof(long long));
+  return LBM_OK;
+}
+
+int lbm_set_tile(lbm_sim* s, int bx, int by) {
+  if (!s) return fail(LBM_EINVAL, "null handle");
+  const int t = bx * by;
+  if (bx < 16 || bx % 16 || by < 1 || (t != 64 && t != 128 && t != 256 && t != 512))
+    return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by in {64,128,256,512}");
+  s->T = tiling_of(s->P, bx, by);
+  drop_graphs(s);
+  return LBM_OK;
+}
+
+int lbm_get_tile(const lbm_sim* s, int* bx, int* by) {
+  if (!s || !bx || !by) return fail(LBM_EINVAL, "null argument");
+  *bx = s->T.bx;
+  *by = s->T.by;
+  return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_sim* s, int n, double* out_ms) {
+  if (!s || n < 1 || !out_ms) return fail(LBM_EINVAL, "bad argument");
+  const int K = 4;
+  hipEvent_t ev[4 * 64];
+  const int batch = std::min(n, 64);
+  for (int i = 0; i < K * batch; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  double acc[3] = {0, 0, 0};
+  int done = 0;
+  int rc = LBM_OK;
+  while (done < n && rc == LBM_OK) {
+    const int m = std::min(batch, n - done);
+    for (int i = 0; i < m; ++i) {
+      hipError_t e = launch_step(s, s->parity(), s->stream, &ev[K * i]);
+      if (e != hipSuccess) {
+        rc = fail(LBM_EDEVICE, hipGetErrorString(e));
+        break;
+      }
+      s->steps += 1;
+    }
+    if (rc) break;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+      rc = fail(LBM_EDEVICE, "synchronize");
+      break;
+    }
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ev[K * i + k], ev[K * i + k + 1]);
+        acc[k] += ms;
+      }
+    done += m;
+  }
+  for (int i = 0; i < K * batch; ++i) hipEventDestroy(ev[i]);
+  if (rc) return rc;
+  for (int k = 0; k < 3; ++k) out_ms[k] = acc[k] / n;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_sim* s) {
+  if (!s) return;
+  drop_graphs(s);
+  if (s->part) hipFree(s->part);
+  if (s->res) hipFree(s->res);
+  if (s->res_host) hipHostFree(s->res_host);
+  if (s->cap) hipStreamDestroy(s->cap);
+  delete s;
+}
+
+}  // extern "C"

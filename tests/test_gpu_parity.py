@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (FP32 storage and compute, after 1000 steps unless stated):
+  max |phi_gpu - phi_oracle| <= 1e-5,
+  max |u_gpu - u_oracle| / max(max |u_oracle|, U_ref) <= 1e-4,
+with U_ref = sigma / mu_H for the drop, sqrt(g L) for Rayleigh-Taylor and u_j
+for jets.  16-bit storage: max |phi_gpu - phi_oracle| <= 1e-3."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a GPU")
+    from paper_2505_12205_amd import lbm
+    return lbm
+
+
+def _run_gpu(cfg, phi0, u0, steps, storage="fp32", tile=None):
+    lbm = _lbm()
+    _log(f"[gpu] {cfg.get('name', cfg['q'])} storage={storage} steps={steps} tile={tile}")
+    s = lbm.Sim(cfg, phi0, u0, storage=storage)
+    if tile:
+        s.set_tile(*tile)
+    s.step(steps)
+    phi, u, p = s.fields()
+    return s, phi.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64), p.cpu().numpy()
+
+
+def _run_oracle(cfg, phi0, u0, steps):
+    o = oracle.Oracle(cfg).init(phi0, u0)
+    o.step(steps)
+    phi, u, p = o.fields()
+    return o, phi, u, p
+
+
+def _errors(phi_g, u_g, phi_o, u_o, uref):
+    ephi = np.abs(phi_g - phi_o).max()
+    eu = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), uref)
+    return ephi, eu
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_cached(key, cfg, phi0, u0, steps):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = _run_oracle(cfg, phi0, u0, steps)
+    return _ORACLE_CACHE[key]
+
+
+def test_drop2d_fp32_1000_steps():
+    cfg, phi0, u0 = W.drop2d()
+    _, phi_o, u_o, _ = _oracle_cached("drop", cfg, phi0, u0, 1000)
+    _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 1000)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o, cfg["sigma"] / (cfg["rho_h"] * cfg["tau_h"] / 3))
+    _log(f"drop2d: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+    assert ephi <= 1e-5 and eu <= 1e-4
+
+
+def _rt_copy(nx, ny, nz, seed=None):
+    cfg, phi0, u0 = W.rt3d(nx=nx, ny=ny, nz=nz, lref=256)
+    if seed is not None:
+        phi0, u0 = W.perturb(phi0, u0, seed, 0.01, 1e-3)
+    return cfg, phi0, u0
+
+
+def test_rt3d_copy_fp32_1000_steps():
+    cfg, phi0, u0 = _rt_copy(32, 48, 16, seed=21)
+    _, phi_o, u_o, _ = _oracle_cached("rt", cfg, phi0, u0, 1000)
+    _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 1000)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o, 0.04)
+    _log(f"rt3d copy: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+    assert ephi <= 1e-5 and eu <= 1e-4
+
+
+@pytest.mark.parametrize("shape,tile", [((37, 29, 11), (64, 4)), ((37, 29, 11), (32, 8)),
+                                        ((3, 5, 4), (16, 4)), ((70, 9, 3), (128, 2))])
+def test_rt3d_ragged_tiles(shape, tile):
+    cfg, phi0, u0 = _rt_copy(*shape, seed=5)
+    _, phi_o, u_o, _ = _run_oracle(cfg, phi0, u0, 101)
+    _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 101, tile=tile)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o, 0.04)
+    _log(f"ragged {shape} {tile}: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+    assert ephi <= 1e-5 and eu <= 1e-4
+
+
+def _jet_copy(nx=24, ny=24, nz=48, radius=6.0, seed=None):
+    cfg, phi0, u0 = W.jet3d(nx=nx, ny=ny, nz=nz, radius=radius, param_radius=12.0, stub=10.0)
+    if seed is not None:
+        phi0, u0 = W.perturb(phi0, u0, seed, 0.01, 1e-3)
+    return cfg, phi0, u0
+
+
+def test_jet_copy_fp32_inlet_outlet_freeslip():
+    cfg, phi0, u0 = _jet_copy(seed=3)
+    _, phi_o, u_o, _ = _oracle_cached("jet", cfg, phi0, u0, 1000)
+    _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 1000)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o, cfg["inlet_u"])
+    _log(f"jet copy fp32: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+    assert ephi <= 1e-5 and eu <= 1e-4
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_jet_copy_16bit_storage(storage):
+    cfg, phi0, u0 = _jet_copy(seed=3)
+    _, phi_o, u_o, p_o = _oracle_cached("jet", cfg, phi0, u0, 1000)
+    _, phi_g, u_g, p_g = _run_gpu(cfg, phi0, u0, 1000, storage=storage)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o, cfg["inlet_u"])
+    ep = np.abs(p_g - p_o).max()
+    _log(f"jet copy {storage}: max|dphi|={ephi:.3e} rel_u={eu:.3e} max|dp|={ep:.3e}")
+    assert ephi <= 1e-3
+
+
+def test_drop2d_16bit_storage():
+    cfg, phi0, u0 = W.drop2d()
+    _, phi_o, u_o, _ = _oracle_cached("drop", cfg, phi0, u0, 1000)
+    for storage in ("fp16", "bf16"):
+        _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 1000, storage=storage)
+        ephi, eu = _errors(phi_g, u_g, phi_o, u_o, 1e-3)
+        _log(f"drop2d {storage}: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+        if storage == "fp16":
+            assert ephi <= 1e-3
+
+
+def test_one_step_both_parities_against_oracle_at_every_node():
+    """One even and one odd step from an exported state, every node."""
+    lbm = _lbm()
+    cfg, phi0, u0 = _jet_copy(nx=20, ny=18, nz=30, radius=5.0, seed=9)
+    s = lbm.Sim(cfg, phi0, u0)
+    s.step(6)
+    for k in range(2):
+        h, g, u = [t.cpu().numpy() for t in s.export_state()]
+        _log(f"[gpu] one-step parity={s.steps_done % 2}")
+        s.step(1)
+        h1, g1, u1 = [t.cpu().numpy() for t in s.export_state()]
+        nodes = np.arange(h.shape[1] * h.shape[2] * h.shape[3])
+        ho, go, uo = oracle.step_nodes_f32(cfg, h, g, u, nodes)
+        q = cfg["q"]
+        eh = np.abs(h1.reshape(q, -1).T - ho).max()
+        eg = np.abs(g1.reshape(q, -1).T - go).max()
+        eu = np.abs(u1.reshape(3, -1).T - uo).max()
+        _log(f"one step: max|dh|={eh:.3e} max|dg|={eg:.3e} max|du|={eu:.3e}")
+        assert eh < 2e-7 and eg < 2e-7 and eu < 2e-7
+
+
+def test_full_size_rt_sampled_one_step():
+    """Rayleigh-Taylor at 256x1024x256 in the benchmark's launch shape: one
+    even and one odd step checked at sampled nodes against the oracle's
+    one-node evaluation from the exported full state."""
+    lbm = _lbm()
+    cfg, phi0, u0 = W.rt3d()
+    s = lbm.Sim(cfg, phi0, u0)
+    del phi0
+    s.step(4)
+    rng = np.random.default_rng(12205)
+    N = 256 * 1024 * 256
+    nodes = np.unique(np.concatenate([
+        rng.integers(0, N, 400),
+        # walls, periodic seams and the interface band
+        [0, 255, 256 * 1023, N - 1, 256 * 1024 * 128 + 256 * 512 + 7,
+         256 * 511 + 3, 256 * 512 + 255, 256 * 1024 * 255 + 256 * 513]]))
+    for k in range(2):
+        _log(f"[gpu] full-size RT sampled step, parity={s.steps_done % 2}")
+        h, g, u = s.export_state()
+        hc, gc, uc = h.cpu().numpy(), g.cpu().numpy(), u.cpu().numpy()
+        del h, g, u
+        s.step(1)
+        h1, g1, u1 = s.export_state()
+        import torch
+        idx = torch.as_tensor(nodes, device=h1.device)
+        h1s = h1.reshape(19, -1)[:, idx].T.cpu().numpy()
+        g1s = g1.reshape(19, -1)[:, idx].T.cpu().numpy()
+        u1s = u1.reshape(3, -1)[:, idx].T.cpu().numpy()
+        del h1, g1, u1
+        ho, go, uo = oracle.step_nodes_f32(cfg, hc, gc, uc, nodes)
+        del hc, gc, uc
+        eh, eg, eu = np.abs(h1s - ho).max(), np.abs(g1s - go).max(), np.abs(u1s - uo).max()
+        _log(f"full RT sampled: max|dh|={eh:.3e} max|dg|={eg:.3e} max|du|={eu:.3e}")
+        assert eh < 2e-7 and eg < 2e-7 and eu < 2e-7
+
+
+def test_mass_conservation_fp32():
+    lbm = _lbm()
+    cfg, phi0, u0 = _rt_copy(64, 128, 32, seed=1)
+    s = lbm.Sim(cfg, phi0, u0)
+    m0, _ = s.reduce()
+    s.step(1000)
+    m1, k1 = s.reduce()
+    _log(f"mass drift {abs(m1 - m0) / m0:.3e}")
+    assert abs(m1 - m0) / m0 <= 1e-6 and np.isfinite(k1)
+
+
+def test_reduce_matches_oracle():
+    lbm = _lbm()
+    cfg, phi0, u0 = W.drop2d()
+    s = lbm.Sim(cfg, phi0, u0)
+    s.step(100)
+    o = oracle.Oracle(cfg).init(phi0, u0).step(100)
+    mg, kg = s.reduce()
+    mo, ko = o.reduce()
+    assert abs(mg - mo) / mo < 1e-6
+    assert abs(kg - ko) <= 1e-3 * ko + 1e-18
+
+
+def test_deterministic_and_step_splitting():
+    """Two runs are bitwise equal; 1+3+... single/graph splits equal one call."""
+    lbm = _lbm()
+    cfg, phi0, u0 = _jet_copy(seed=4)
+    a = lbm.Sim(cfg, phi0, u0).step(57)
+    b = lbm.Sim(cfg, phi0, u0)
+    for n in (1, 3, 2, 40, 11):
+        b.step(n)
+    ha, ga, ua = a.export_state()
+    hb, gb, ub = b.export_state()
+    assert (ha == hb).all() and (ga == gb).all() and (ua == ub).all()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_export_import_and_checkpoint_roundtrip(storage):
+    lbm = _lbm()
+    cfg, phi0, u0 = _jet_copy(seed=6)
+    a = lbm.Sim(cfg, phi0, u0, storage=storage).step(31)
+    blob = a.save()
+    h, g, u = a.export_state()
+    b = lbm.Sim(cfg, phi0, u0, storage=storage).import_state(h, g, u)
+    h2, g2, u2 = b.export_state()
+    if storage == "fp32":
+        assert (h2 == h).all() and (g2 == g).all() and (u2 == u).all()
+    else:
+        assert (h2 - h).abs().max().item() < 1e-3
+    a.step(20)
+    c = lbm.Sim(cfg, phi0, u0, storage=storage).load(blob).step(20)
+    ha, ga, _ = a.export_state()
+    hc, gc, _ = c.export_state()
+    assert (ha == hc).all() and (ga == gc).all()
+
+
+def test_zero_steps_and_tiny_domain():
+    lbm = _lbm()
+    cfg, phi0, u0 = _rt_copy(2, 4, 2, seed=2)
+    s = lbm.Sim(cfg, phi0, u0).step(0)
+    h0, g0, _ = s.export_state()
+    o = oracle.Oracle(cfg).init(phi0, u0)
+    ho, go, _ = o.state()
+    assert np.abs(h0.cpu().numpy() - ho).max() < 1e-6
+    s.step(9)
+    o.step(9)
+    phi_g, u_g, _ = s.fields()
+    phi_o, u_o, _ = o.fields()
+    assert np.abs(phi_g.cpu().numpy() - phi_o).max() < 1e-5
