@@ -818,7 +818,9 @@ static void compute_phi(ora_sim* s) {
 
 /* reading (initial populations; the paper gives none): u^{-1} = u0,
  * h_a = h^eq_a(phi0, u0) - F^phi_a / 2 (so that sum_a h_a = phi0 exactly) and
- * g_a = f^eq_a(p* = 0, u0). */
+ * g_a = f^eq_a(p* = 0, u0).  The initial state is a post-boundary state: at
+ * velocity-inlet nodes the populations entering from beyond the inlet are
+ * set by the inlet condition from the others, as after every streaming. */
 int ora_init(ora_sim* s, const double* phi0, const double* u0) {
   const lattice_t* L = s->L;
   const long N = s->N;
@@ -842,6 +844,25 @@ int ora_init(ora_sim* s, const double* phi0, const double* u0) {
     for (int a = 0; a < L->q; ++a) {
       s->h[a * N + i] = heq[a] - 0.5 * fphi[a];
       s->g[a * N + i] = feq[a];
+    }
+  }
+  for (long i = 0; i < N; ++i) {
+    int x[3];
+    coords(&s->P, i, x);
+    int f = inlet_face_of(&c, x);
+    if (f < 0) continue;
+    double hn[QMAX], gn[QMAX], n[3];
+    int unknown[QMAX];
+    inward_normal(f, n);
+    for (int a = 0; a < L->q; ++a) {
+      hn[a] = s->h[a * N + i];
+      gn[a] = s->g[a * N + i];
+      unknown[a] = (L->e[a][0] * n[0] + L->e[a][1] * n[1] + L->e[a][2] * n[2]) > 0.0;
+    }
+    apply_inlet(&c, x, f, hn, gn, unknown);
+    for (int a = 0; a < L->q; ++a) {
+      s->h[a * N + i] = hn[a];
+      s->g[a * N + i] = gn[a];
     }
   }
   return 0;

@@ -394,6 +394,21 @@ __device__ __forceinline__ bool tile_coords(const KParams& P, const Tiling& T, i
   return c[0] < P.nx && c[1] < P.ny;
 }
 
+// Kahan-compensated sum v[0] + ... + v[Q-1] = hi + lo
+template <int Q>
+__device__ __forceinline__ void kahan_sum(const float* v, float& hi, float& lo) {
+  float s = 0.0f, c = 0.0f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const float y = v[a] - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  hi = s;
+  lo = -c;
+}
+
 // ---------------------------------------------------------------------------
 // k_phi: phase field of the current state
 // ---------------------------------------------------------------------------
@@ -408,11 +423,9 @@ __global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T) {
     inlet_tangential<Q>(c, p0, p1);
     phi = inlet_psi(P, p0, p1);  // sum_a h_a = phi_in exactly after the inlet condition
   } else {
-    float h[Q], g[1];
+    float h[Q], g[1], lo;
     load_node<Q, ST, ODD, false>(P, B, c, h, g);
-    phi = 0.0f;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) phi += h[a];
+    kahan_sum<Q>(h, phi, lo);
   }
   B.phi_out[node] = phi;
 }
@@ -420,6 +433,7 @@ __global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T) {
 // ---------------------------------------------------------------------------
 // node physics
 // ---------------------------------------------------------------------------
+
 struct Stress {  // second moments sum g e e
   float xx, yy, zz, xy, yz, xz;
 };
@@ -538,16 +552,30 @@ __global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T) {
     const float nrm = rsqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + 1e-24f);
     const float tn[3] = {theta * gr[0] * nrm, theta * gr[1] * nrm, theta * gr[2] * nrm};
     const float om = P.omega_h;
-    Ty* __restrict__ H = (Ty*)B.h;
+    float pre_hi, pre_lo;
+    kahan_sum<Q>(h, pre_hi, pre_lo);
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
       const float w = L::w[a];
       const float eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
-      const float heq = phi * w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+      // h^eq = phi Gamma_a with phi = sum_a h_a carried as pre_hi + pre_lo
+      const float Ga = w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+      const float heq = fmaf(pre_hi, Ga, pre_lo * Ga);
       const float fphi = w * (L::ex[a] * tn[0] + L::ey[a] * tn[1] + L::ez[a] * tn[2]);
-      const float hp = h[a] - om * (h[a] - heq + 0.5f * fphi) + fphi;
+      h[a] = h[a] - om * (h[a] - heq + 0.5f * fphi) + fphi;
+    }
+    // The collision conserves sum_a h_a exactly (sum Gamma_a = 1, sum F^phi_a
+    // = 0), but the FP32 weights sum to 1 + O(1e-8), which would add a
+    // systematic mass drift each step; restore the node's mass with
+    // compensated sums (a zero correction in exact arithmetic).
+    float post_hi, post_lo;
+    kahan_sum<Q>(h, post_hi, post_lo);
+    h[0] += (pre_hi - post_hi) + (pre_lo - post_lo);
+    Ty* __restrict__ H = (Ty*)B.h;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
       int sp, sn;
-      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_h(H, (size_t)sp * N + sn, hp, 1.0f / w, phi);
+      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_h(H, (size_t)sp * N + sn, h[a], 1.0f / L::w[a], phi);
     }
   }
 

@@ -150,7 +150,7 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and lib is not None:
             try:
                 self.synchronize()
             except Exception:

