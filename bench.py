@@ -30,13 +30,17 @@ def algorithmic_bytes_per_node(q: int, d: int, pop_bytes: int):
     return 2 * 2 * q * pop_bytes + 2 * d * 4 + 8, kstep, kphi
 
 
-def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None):
+def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True):
     import torch
 
     from paper_2505_12205_amd import lbm
     sim = lbm.Sim(cfg, phi0, u0, storage=storage)
     if tile:
         sim.set_tile(*tile)
+    elif autotune:
+        choice = sim.autotune(trial_steps=6)
+        print(f"[bench] {storage} autotune -> tile {choice[0]}x{choice[1]} nontemporal={choice[2]} "
+              f"{choice[3]:.3f} ms/step", file=sys.stderr, flush=True)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -46,6 +50,23 @@ def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None):
     kt = sim.kernel_times(min(steps, 20))
     mass, ke = sim.reduce()
     return sim, dt, kt, mass, ke
+
+
+def copy_probe(gib: float = 2.0, reps: int = 10):
+    """Device-to-device copy of a buffer of known size (torch's copy kernel):
+    the practical HBM ceiling, and the calibration run for the byte counters."""
+    import torch
+    n = int(gib * (1 << 30) // 4)
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return 2 * n * 4 / dt / 1e9
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -79,6 +100,9 @@ def main():
     ap.add_argument("--forms", default="fp16,bf16",
                     help="comma list of 16-bit storage forms to time beside FP32 ('' for none)")
     ap.add_argument("--tile", default="", help="bx,by launch shape of the fused kernel")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="only run the 2 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -91,12 +115,17 @@ def main():
         sys.exit(1)
     from paper_2505_12205_amd import workloads as W
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    copy_gbs = copy_probe()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    if args.copy_probe_only:
+        return
 
     cfg, phi0, u0 = W.rt3d()
     N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     print(f"[bench] workload {cfg['name']} N={N} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
-    sim, dt, kt, mass, ke = run_gpu(cfg, phi0, u0, "fp32", args.steps, args.warmup, tile)
+    sim, dt, kt, mass, ke = run_gpu(cfg, phi0, u0, "fp32", args.steps, args.warmup, tile,
+                                    not args.no_autotune)
     mlups = N * args.steps / dt / 1e6
     b_step, b_k, b_phi = algorithmic_bytes_per_node(19, 3, 4)
     achieved = b_k * N / (kt[1] * 1e-3) / 1e9
@@ -108,7 +137,8 @@ def main():
 
     forms = {}
     for st in [f for f in args.forms.split(",") if f]:
-        s2, dt2, kt2, _, _ = run_gpu(cfg, phi0, u0, st, max(20, args.steps // 2), 5, tile)
+        s2, dt2, kt2, _, _ = run_gpu(cfg, phi0, u0, st, max(20, args.steps // 2), 5, tile,
+                                     not args.no_autotune)
         n2 = max(20, args.steps // 2)
         _, bk2, _ = algorithmic_bytes_per_node(19, 3, 2)
         forms[st] = {"MLUPS": round(N * n2 / dt2 / 1e6, 1),
@@ -138,7 +168,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_step (fused macroscopic + collisions + AA streaming)",
                      "bytes_per_node": b_k, "kernel_ms": round(kt[1], 4),
-                     "phi_pass_ms": round(kt[0], 4)},
+                     "phi_pass_ms": round(kt[0], 4), "device_copy_GBs": round(copy_gbs, 1)},
         "step_bytes_per_node": b_step,
         "mass": mass,
         "kinetic": ke,

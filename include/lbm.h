@@ -61,8 +61,9 @@ typedef enum {
 
 /* Population storage.  FP32 stores populations as they are.  The 16-bit
  * forms store deviations from the lattice-weight rest value, decoded to FP32
- * in registers: g_a / w_a, and (h_a - w_a phi_src) / w_a with phi_src the
- * phase field of the node that produced the population. */
+ * in registers: g_a / w_a, and (h_a - w_a phi_ref) / w_a with phi_ref the
+ * phase field, at the step the value was written, of the node that reads it
+ * (the node it streams into). */
 typedef enum { LBM_FP32 = 0, LBM_FP16_DEV = 1, LBM_BF16_DEV = 2 } lbm_storage;
 
 /* Body force: rho g (Poiseuille channel) or (rho - rho_L) g (jets). */
@@ -148,6 +149,17 @@ int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes);
  * (bx * by must be 64, 128, 256 or 512; bx a multiple of 16). */
 int lbm_set_tile(lbm_sim* s, int bx, int by);
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by);
+
+/* Non-temporal hint (nonzero) on the population stores of the fused kernel. */
+int lbm_set_store_hint(lbm_sim* s, int nontemporal);
+
+/* Autotuner: times trial_steps eager steps for each candidate tile shape and
+ * store hint and keeps the fastest; results are cached per (lattice, storage,
+ * grid, boundary set) for the life of the process, so later simulations of
+ * the same shape take the cached choice without trials.  The state advances
+ * by the trial steps.  Synchronises.  Outputs (nullable): chosen bx, by,
+ * hint, and its mean ms per step. */
+int lbm_autotune(lbm_sim* s, int trial_steps, int* bx, int* by, int* nontemporal, double* ms_per_step);
 
 /* Time the step's kernels over n eager steps with HIP events on the
  * simulation's stream; out_ms[0] = mean phase-field pass, out_ms[1] = mean

@@ -45,7 +45,7 @@ struct KBufs {
   float* u;                // 3*N, u[d*N + node]
   const float* phi;        // phase field of this step (stencil)
   float* phi_out;          // written by k_phi
-  const float* ref;        // phase field the stored populations were encoded with (16-bit forms)
+  const float* ref;        // 16-bit forms: phase field (previous step) of each stored value's reader
   float* obuf;             // outlet plane: h then g, (2Q) * plane
 };
 
@@ -55,26 +55,44 @@ struct KBufs {
 template <int ST>
 struct Codec;
 
+// store with an optional non-temporal hint (the written populations are not
+// read again within the step, so they need not stay in L2)
+template <bool NT, typename T, typename I>
+__device__ __forceinline__ void put(T* p, I i, T v) {
+  if (NT)
+    __builtin_nontemporal_store(v, p + i);
+  else
+    p[i] = v;
+}
+
 template <>
 struct Codec<0> {  // FP32 as is
   using T = float;
-  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) { return p[i]; }
-  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) { p[i] = v; }
-  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return p[i]; }
-  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = v; }
+  template <typename I>
+  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) { return p[i]; }
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) { put<NT>(p, i, v); }
+  template <typename I>
+  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return p[i]; }
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, v); }
 };
 
 template <>
-struct Codec<1> {  // FP16 deviations: h -> h/w - phi_src, g -> g/w
+struct Codec<1> {  // FP16 deviations: h -> h/w - phi_ref, g -> g/w
   using T = _Float16;
-  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) {
+  template <typename I>
+  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) {
     return w * ((float)p[i] + ref);
   }
-  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) {
-    p[i] = (T)(v * iw - ref);
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) {
+    put<NT>(p, i, (T)(v * iw - ref));
   }
-  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return w * (float)p[i]; }
-  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = (T)(v * iw); }
+  template <typename I>
+  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return w * (float)p[i]; }
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, (T)(v * iw)); }
 };
 
 __device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
@@ -87,14 +105,18 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uin
 template <>
 struct Codec<2> {  // BF16 deviations, same encoding as FP16
   using T = uint16_t;
-  static __device__ __forceinline__ float ld_h(const T* p, size_t i, float w, float ref) {
+  template <typename I>
+  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) {
     return w * (bf2f(p[i]) + ref);
   }
-  static __device__ __forceinline__ void st_h(T* p, size_t i, float v, float iw, float ref) {
-    p[i] = f2bf(v * iw - ref);
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) {
+    put<NT>(p, i, f2bf(v * iw - ref));
   }
-  static __device__ __forceinline__ float ld_g(const T* p, size_t i, float w) { return w * bf2f(p[i]); }
-  static __device__ __forceinline__ void st_g(T* p, size_t i, float v, float iw) { p[i] = f2bf(v * iw); }
+  template <typename I>
+  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return w * bf2f(p[i]); }
+  template <bool NT = false, typename I = size_t>
+  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, f2bf(v * iw)); }
 };
 
 // ---------------------------------------------------------------------------
@@ -225,6 +247,48 @@ __device__ __forceinline__ bool resolve_dst(const KParams& P, const int c[3], in
   return true;
 }
 
+// Node that receives post-collision population a of node c after streaming
+// (the reader of the stored value at the next step).  Returns 0 if it leaves
+// the domain through the inlet or outlet, 1 for the plain (possibly
+// periodically wrapped) neighbour c + e_a, 2 for a wall-reflected target.
+template <int Q>
+__device__ __forceinline__ int stream_target(const KParams& P, const int c[3], int a, int& node) {
+  int t[3];
+  int mask = 0;
+  bool noslip = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e = ecomp<Q>(a, d);
+    t[d] = c[d] + e;
+    if (e == 0) continue;
+    const int n = dim_of(P, d);
+    if (t[d] < 0 || t[d] >= n) {
+      const int b = P.bc[2 * d + (t[d] >= n ? 1 : 0)];
+      if (b == BC_PERIODIC) {
+        t[d] = t[d] < 0 ? t[d] + n : t[d] - n;
+      } else if (b == BC_INLET || b == BC_OUTLET) {
+        return 0;
+      } else {
+        mask |= 1 << d;
+        noslip |= (b == BC_NOSLIP);
+      }
+    }
+  }
+  if (mask == 0) {
+    node = node_of(P, t[0], t[1], t[2]);
+    return 1;
+  }
+  if (noslip) {
+    node = node_of(P, c[0], c[1], c[2]);
+    return 2;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    if (mask >> d & 1) t[d] = c[d];
+  node = node_of(P, t[0], t[1], t[2]);
+  return 2;
+}
+
 // nozzle profile psi = 1/2 [1 + tanh(2 (R - r)/xi)] at tangential position (p0, p1)
 __device__ __forceinline__ float inlet_psi(const KParams& P, float p0, float p1) {
   const float d0 = p0 - P.in_c0, d1 = p1 - P.in_c1;
@@ -342,8 +406,8 @@ __device__ __forceinline__ void load_node(const KParams& P, const KBufs& B, cons
                                           float* g) {
   using C = Codec<ST>;
   using T = typename C::T;
-  const T* __restrict__ H = (const T*)B.h;
-  const T* __restrict__ G = (const T*)B.g;
+  const T* H = (const T*)B.h;  // not restrict: the same arrays are written in place
+  const T* G = (const T*)B.g;
   const size_t N = (size_t)P.N;
   if (is_outlet_node<Q>(P, c)) {
     const int pi = plane_index<Q>(P, c);
@@ -355,11 +419,13 @@ __device__ __forceinline__ void load_node(const KParams& P, const KBufs& B, cons
     return;
   }
   const bool inlet = is_inlet_node<Q>(P, c);
+  // 16-bit forms: every stored h value was encoded relative to the phase
+  // field (previous step) of the node that reads it, i.e. this node
+  const float ref = (ST == 0) ? 0.0f : B.ref[node_of(P, c[0], c[1], c[2])];
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     int sp, sn, src;
     if (resolve_src<Q, ODD>(P, c, a, sp, sn, src)) {
-      const float ref = (ST == 0) ? 0.0f : B.ref[src];
       h[a] = C::ld_h(H, (size_t)sp * N + sn, Lat<Q>::w[a], ref);
       if (LOAD_G) g[a] = C::ld_g(G, (size_t)sp * N + sn, Lat<Q>::w[a]);
     } else {
@@ -431,9 +497,8 @@ __global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T) {
 }
 
 // ---------------------------------------------------------------------------
-// node physics
+// node physics (shared by the fast interior path and the general path)
 // ---------------------------------------------------------------------------
-
 struct Stress {  // second moments sum g e e
   float xx, yy, zz, xy, yz, xz;
 };
@@ -460,33 +525,337 @@ __device__ __forceinline__ void viscous_force(const Stress& S, float p, const fl
   F[2] = (D == 3) ? -tau * (Txz * gr[0] + Tyz * gr[1] + Tzz * gr[2]) : 0.0f;
 }
 
+// accumulate p* = sum g, j = sum g e, Pi = sum g e e
+template <int Q>
+__device__ __forceinline__ void add_moments(int a, float v, float& p, float j[3], Stress& S) {
+  using L = Lat<Q>;
+  p += v;
+  if (L::ex[a]) { j[0] += L::ex[a] * v; S.xx += v; }
+  if (L::ey[a]) { j[1] += L::ey[a] * v; S.yy += v; }
+  if (L::D == 3 && L::ez[a]) { j[2] += L::ez[a] * v; S.zz += v; }
+  if (L::ex[a] && L::ey[a]) S.xy += (L::ex[a] * L::ey[a]) * v;
+  if (L::D == 3 && L::ey[a] && L::ez[a]) S.yz += (L::ey[a] * L::ez[a]) * v;
+  if (L::D == 3 && L::ex[a] && L::ez[a]) S.xz += (L::ex[a] * L::ez[a]) * v;
+}
+
+// everything both collisions need, from the stencil and the moments of g
+struct NodeCtx {
+  float phi, u[3], uu, om, tn[3];  // phase-field collision
+  float p, f3r, F[3];              // hydrodynamic equilibrium and forcing
+  float cxx, cyy, czz, cxy, cyz, cxz;  // (1 - s) times the stress-projection coefficients
+};
+
+// Macroscopic update (Eqs. density_interpolation, chemical_potential,
+// surface_tension_force, density_gradient_phase_field, relaxation_time,
+// pressure_force, total_force, velocity_update) and the collision constants.
+template <int Q>
+__device__ __forceinline__ void macro(const KParams& P, float phi, const float gr[3], float lap, float p,
+                                      const float j[3], const Stress& S, const float up[3], NodeCtx& X) {
+  constexpr int D = Lat<Q>::D;
+  const float phc = P.clamp ? fminf(fmaxf(phi, 0.0f), 1.0f) : phi;
+  const float rho = P.rho_l + phc * P.drho;
+  const float inv_rho = 1.0f / rho;
+  const float mu = P.beta4 * phi * (phi - 1.0f) * (phi - 0.5f) - P.kappa * lap;  // bulk term sign-corrected
+  const float fb = rho - P.fb_rhol;
+  float Fsb[3], grho[3];
+  Fsb[0] = mu * gr[0] + fb * P.gx;
+  Fsb[1] = mu * gr[1] + fb * P.gy;
+  Fsb[2] = mu * gr[2] + fb * P.gz;
+  grho[0] = P.drho * gr[0];
+  grho[1] = P.drho * gr[1];
+  grho[2] = P.drho * gr[2];
+  const float tau = P.tau_l + phc * P.dtau;
+  const float s = 1.0f / (tau + 0.5f);
+  const float p3 = p * (1.0f / 3.0f);
+  // velocity with the viscous force evaluated at the stored velocity
+  float Fm[3];
+  viscous_force<D>(S, p, up, tau, s, grho, Fm);
+  float u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[d] = j[d] + 0.5f * (Fsb[d] - p3 * grho[d] + Fm[d]) * inv_rho;
+  if (D == 2) u[2] = 0.0f;
+  // collision force with the viscous force re-evaluated at u^n
+  float Fc[3];
+  viscous_force<D>(S, p, u, tau, s, grho, Fc);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    X.u[d] = u[d];
+    X.F[d] = Fsb[d] - p3 * grho[d] + Fc[d];
+  }
+  X.uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  X.phi = phi;
+  X.p = p;
+  X.f3r = 3.0f * inv_rho;
+  // phase-field forcing direction (Eq. forcing_term)
+  const float theta = (1.0f - 4.0f * (phi - 0.5f) * (phi - 0.5f)) * P.inv_xi;
+  const float nrm = rsqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + 1e-24f);
+  X.tn[0] = theta * gr[0] * nrm;
+  X.tn[1] = theta * gr[1] * nrm;
+  X.tn[2] = theta * gr[2] * nrm;
+  X.om = P.omega_h;
+  // WMRT: only the deviatoric second moments of g - fbar, dev(Pi - u u), keep
+  // a (1 - s) share; the projection coefficients follow
+  const float dxx = S.xx - u[0] * u[0], dyy = S.yy - u[1] * u[1];
+  const float dzz = (D == 3) ? S.zz - u[2] * u[2] : 0.0f;
+  const float dxy = S.xy - u[0] * u[1];
+  const float dyz = (D == 3) ? S.yz - u[1] * u[2] : 0.0f;
+  const float dxz = (D == 3) ? S.xz - u[0] * u[2] : 0.0f;
+  const float one_s = 1.0f - s;
+  if (D == 3) {  // weighted basis: P y = 4.5 w_a (e e : dev)
+    const float tr = (dxx + dyy + dzz) * (1.0f / 3.0f);
+    X.cxx = 4.5f * one_s * (dxx - tr);
+    X.cyy = 4.5f * one_s * (dyy - tr);
+    X.czz = 4.5f * one_s * (dzz - tr);
+    X.cxy = 9.0f * one_s * dxy;
+    X.cyz = 9.0f * one_s * dyz;
+    X.cxz = 9.0f * one_s * dxz;
+  } else {  // plain orthogonal D2Q9 basis: P y = [(ex^2-ey^2)(dxx-dyy) + ex ey dxy] / 4
+    X.cxx = 0.25f * one_s * (dxx - dyy);
+    X.cyy = -X.cxx;
+    X.czz = 0.0f;
+    X.cxy = 0.25f * one_s * dxy;
+    X.cyz = X.cxz = 0.0f;
+  }
+}
+
+// post-collision h_a (Eqs. lbe_interface, forcing_term, equilibrium_with_force,
+// equilibrium_function)
+template <int Q>
+__device__ __forceinline__ float h_post(const NodeCtx& X, int a, float ha) {
+  using L = Lat<Q>;
+  const float w = L::w[a];
+  const float eu = L::ex[a] * X.u[0] + L::ey[a] * X.u[1] + L::ez[a] * X.u[2];
+  const float heq = X.phi * w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * X.uu);
+  const float fphi = w * (L::ex[a] * X.tn[0] + L::ey[a] * X.tn[1] + L::ez[a] * X.tn[2]);
+  return ha - X.om * (ha - heq + 0.5f * fphi) + fphi;
+}
+
+// post-collision g_a: f^eq + F_a/2 + (1 - s) P(g - fbar)_a, the closed form of
+// Eqs. lbe_standard, mrt_collision, equilibrium_modified, force_term
+template <int Q>
+__device__ __forceinline__ float g_post(const NodeCtx& X, int a) {
+  using L = Lat<Q>;
+  const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
+  const float w = L::w[a];
+  const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
+  const float feq = w * (X.p + 3.0f * eu + 4.5f * eu * eu - 1.5f * X.uu);
+  const float Fa = w * X.f3r * (ex * X.F[0] + ey * X.F[1] + ez * X.F[2]);
+  float proj = 0.0f;
+  if (ex) proj += X.cxx;
+  if (ey) proj += X.cyy;
+  if (ez) proj += X.czz;
+  if (ex && ey) proj += (ex * ey) * X.cxy;
+  if (ey && ez) proj += (ey * ez) * X.cyz;
+  if (ex && ez) proj += (ex * ez) * X.cxz;
+  if (L::D == 3) proj *= w;
+  return feq + 0.5f * Fa + proj;
+}
+
+__device__ __forceinline__ void kahan_add(float v, float& s, float& c) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// stencil sums of phi (Eqs. gradient_phi, laplacian_phi; c = dx = 1)
+template <int Q>
+__device__ __forceinline__ void stencil_add(int a, float pn, float phi, float gr[3], float& lap) {
+  using L = Lat<Q>;
+  const float w = L::w[a];
+  if (L::ex[a]) gr[0] += (w * L::ex[a]) * pn;
+  if (L::ey[a]) gr[1] += (w * L::ey[a]) * pn;
+  if (L::D == 3 && L::ez[a]) gr[2] += (w * L::ez[a]) * pn;
+  lap += w * (pn - phi);
+}
+
+// Neighbour offsets of node c with periodic wrap (only valid where no
+// non-periodic face is touched): n(c + e) = node + ox[ex+1] + oy[ey+1] + oz[ez+1].
+struct Nbr {
+  int node, ox[3], oy[3], oz[3];
+  template <int Q>
+  __device__ __forceinline__ int at(int a) const {
+    return node + ox[Lat<Q>::ex[a] + 1] + oy[Lat<Q>::ey[a] + 1] + oz[Lat<Q>::ez[a] + 1];
+  }
+};
+
+__device__ __forceinline__ Nbr make_nbr(const KParams& P, const int c[3]) {
+  Nbr n;
+  n.node = node_of(P, c[0], c[1], c[2]);
+  const int sxy = P.nx * P.ny;
+  n.ox[0] = c[0] == 0 ? P.nx - 1 : -1;
+  n.ox[1] = 0;
+  n.ox[2] = c[0] == P.nx - 1 ? 1 - P.nx : 1;
+  n.oy[0] = c[1] == 0 ? (P.ny - 1) * P.nx : -P.nx;
+  n.oy[1] = 0;
+  n.oy[2] = c[1] == P.ny - 1 ? (1 - P.ny) * P.nx : P.nx;
+  n.oz[0] = c[2] == 0 ? (P.nz - 1) * sxy : -sxy;
+  n.oz[1] = 0;
+  n.oz[2] = c[2] == P.nz - 1 ? (1 - P.nz) * sxy : sxy;
+  return n;
+}
+
+// true if the node touches a face whose boundary is not periodic
+template <int Q>
+__device__ __forceinline__ bool on_special_face(const KParams& P, const int c[3]) {
+  bool s = false;
+#pragma unroll
+  for (int d = 0; d < Lat<Q>::D; ++d) {
+    const int n = dim_of(P, d);
+    s |= (c[d] == 0 && P.bc[2 * d] != BC_PERIODIC) || (c[d] == n - 1 && P.bc[2 * d + 1] != BC_PERIODIC);
+  }
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // k_step: fused macroscopic update + both collisions + AA streaming
 // ---------------------------------------------------------------------------
-template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T) {
+
+// Interior / periodic node: populations are consumed as they arrive, no
+// per-direction arrays are held.  The h collision conserves sum_a h_a exactly
+// (sum Gamma_a = 1, sum F^phi_a = 0); FP32 rounding (e.g. the FP32 weights
+// sum to 1 + O(1e-8)) would leave a small systematic mass drift per step, so
+// the node's mass is restored on the rest population with compensated sums
+// (a zero correction in exact arithmetic).
+template <int Q, int ST, int ODD, bool NT>
+__device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, const int c[3]) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   using C = Codec<ST>;
   using Ty = typename C::T;
-  int c[3];
-  if (!tile_coords(P, T, c)) return;
+  const Nbr nb = make_nbr(P, c);
+  const int node = nb.node;
+  const unsigned N = (unsigned)P.N;
+  Ty* Gp = (Ty*)B.g;  // loads and stores go through one pointer: in place
+  Ty* Hp = (Ty*)B.h;
+
+  const float phi = B.phi[node];
+  float gr[3] = {0.f, 0.f, 0.f}, lap = 0.f;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) stencil_add<Q>(a, B.phi[nb.at<Q>(a)], phi, gr, lap);
+  gr[0] *= 3.0f;
+  gr[1] *= 3.0f;
+  gr[2] *= 3.0f;
+  lap *= 6.0f;
+
+  // Population a is read from slot (ra_pop, ra_idx) and its post-collision
+  // value goes to the slot abar was read from.  Slots are addressed as a
+  // uniform per-population base plus a 32-bit node index.
+  auto rpop = [&](int a) -> int { return ODD ? L::opp[a] : a; };
+  auto ridx = [&](int a) -> unsigned { return ODD ? (unsigned)nb.at<Q>(L::opp[a]) : (unsigned)node; };
+  const size_t NN = (size_t)P.N;
+
+  // hydrodynamic moments, opposite pairs summed and differenced
+  float g0 = C::ld_g(Gp, (unsigned)node, L::w[0]);
+  float p = g0, j[3] = {0.f, 0.f, 0.f};
+  Stress S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const int b = L::opp[a];
+    if (b < a) continue;
+    const float ga = C::ld_g(Gp + rpop(a) * NN, ridx(a), L::w[a]);
+    const float gb = C::ld_g(Gp + rpop(b) * NN, ridx(b), L::w[b]);
+    const float s = ga + gb, d = ga - gb;
+    p += s;
+    if (L::ex[a]) { j[0] += L::ex[a] * d; S.xx += s; }
+    if (L::ey[a]) { j[1] += L::ey[a] * d; S.yy += s; }
+    if (D == 3 && L::ez[a]) { j[2] += L::ez[a] * d; S.zz += s; }
+    if (L::ex[a] && L::ey[a]) S.xy += (L::ex[a] * L::ey[a]) * s;
+    if (D == 3 && L::ey[a] && L::ez[a]) S.yz += (L::ey[a] * L::ez[a]) * s;
+    if (D == 3 && L::ex[a] && L::ez[a]) S.xz += (L::ex[a] * L::ez[a]) * s;
+  }
+  float up[3];
+  up[0] = B.u[node];
+  up[1] = B.u[N + node];
+  up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
+  NodeCtx X;
+  macro<Q>(P, phi, gr, lap, p, j, S, up, X);
+  B.u[node] = X.u[0];
+  B.u[N + node] = X.u[1];
+  if (D == 3) B.u[2 * N + node] = X.u[2];
+
+  // per-node constants of the pair updates
+  const float gA = X.p - 1.5f * X.uu;  // f^eq: w (gA + 4.5 eu^2 + 3 eu)
+  const float hB = 1.0f - 1.5f * X.uu; // h^eq: phi w (hB + 4.5 eu^2 + 3 eu)
+  const float hf = 0.5f * X.f3r;       // half of F_a / (w e.F)
+  const float om = X.om;
+  const float ref = (ST == 0) ? 0.0f : B.ref[node];
+
+  // rest population
+  const float h0 = C::ld_h(Hp, (unsigned)node, L::w[0], ref);
+  {
+    const float w = L::w[0];
+    const float g0p = w * gA;  // e_0 = 0: no forcing, no stress projection
+    C::template st_g<NT>(Gp, (unsigned)node, g0p, 1.0f / w);
+  }
+  const float d0 = om * (X.phi * L::w[0] * hB - h0);
+  float dsum = d0;  // sum of the increments h+_a - h_a
+
+  // pairs (a, abar): even parts of the equilibria and of the stress
+  // projection are shared, odd parts change sign
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const int b = L::opp[a];
+    if (b < a) continue;
+    const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
+    const float w = L::w[a];
+    Ty* Ha = Hp + rpop(a) * NN;
+    Ty* Hb = Hp + rpop(b) * NN;
+    Ty* Ga = Gp + rpop(a) * NN;
+    Ty* Gb = Gp + rpop(b) * NN;
+    const unsigned ia = ridx(a), ib = ridx(b);
+    const float ha = C::ld_h(Ha, ia, w, ref);
+    const float hb = C::ld_h(Hb, ib, w, ref);
+    const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
+    const float eu2 = eu * eu;
+    // hydrodynamic set
+    float proj = 0.0f;
+    if (ex) proj += X.cxx;
+    if (ey) proj += X.cyy;
+    if (ez) proj += X.czz;
+    if (ex && ey) proj += (ex * ey) * X.cxy;
+    if (ey && ez) proj += (ey * ez) * X.cyz;
+    if (ex && ez) proj += (ex * ez) * X.cxz;
+    if (D == 2) proj *= (1.0f / w);  // the D2Q9 projection is not weighted
+    const float eF = ex * X.F[0] + ey * X.F[1] + ez * X.F[2];
+    const float gsym = w * (gA + 4.5f * eu2 + proj);
+    const float ganti = w * (3.0f * eu + hf * eF);
+    C::template st_g<NT>(Gb, ib, gsym + ganti, 1.0f / w);  // a goes where b was read
+    C::template st_g<NT>(Ga, ia, gsym - ganti, 1.0f / w);
+    // phase-field set
+    const float pw = X.phi * w;
+    const float hsym = pw * (hB + 4.5f * eu2);
+    const float fphi = w * (ex * X.tn[0] + ey * X.tn[1] + ez * X.tn[2]);
+    const float hanti = pw * (3.0f * eu) - 0.5f * fphi;  // odd part of h^eq - F^phi/2
+    const float da = om * (hsym + hanti - ha) + fphi;
+    const float db = om * (hsym - hanti - hb) - fphi;
+    dsum += da + db;
+    const float wra = (ST == 0) ? 0.0f : B.phi[nb.at<Q>(a)];  // readers' phase field
+    const float wrb = (ST == 0) ? 0.0f : B.phi[nb.at<Q>(b)];
+    C::template st_h<NT>(Hb, ib, ha + da, 1.0f / w, wra);
+    C::template st_h<NT>(Ha, ia, hb + db, 1.0f / w, wrb);
+  }
+  // sum_a (h+_a - h_a) vanishes in exact arithmetic (sum Gamma_a = 1, sum
+  // F^phi_a = 0); FP32 leaves O(1e-8) per node per step with a systematic
+  // part (the FP32 weights sum to 1 + O(1e-8)), so it is removed on the rest
+  // population to keep the node's mass.
+  C::template st_h<NT>(Hp, (unsigned)node, h0 + (d0 - dsum), 1.0f / L::w[0], (ST == 0) ? 0.0f : phi);
+}
+
+// Nodes on wall, inlet or outlet faces: general slot resolution with arrays.
+template <int Q, int ST, int ODD, bool NT>
+__device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, const int c[3]) {
+  using L = Lat<Q>;
+  constexpr int D = L::D;
+  using C = Codec<ST>;
+  using Ty = typename C::T;
   const int node = node_of(P, c[0], c[1], c[2]);
   const size_t N = (size_t)P.N;
 
-  // isotropic stencil of phi (Eqs. gradient_phi, laplacian_phi; c = dx = 1)
   const float phi = B.phi[node];
-  float gr[3] = {0.f, 0.f, 0.f};
-  float lap = 0.f;
+  float gr[3] = {0.f, 0.f, 0.f}, lap = 0.f;
 #pragma unroll
-  for (int a = 1; a < Q; ++a) {
-    const float pn = phi_nb<Q>(P, B.phi, c, a);
-    const float w = L::w[a];
-    if (L::ex[a]) gr[0] += (w * L::ex[a]) * pn;
-    if (L::ey[a]) gr[1] += (w * L::ey[a]) * pn;
-    if (D == 3 && L::ez[a]) gr[2] += (w * L::ez[a]) * pn;
-    lap += w * (pn - phi);
-  }
+  for (int a = 1; a < Q; ++a) stencil_add<Q>(a, phi_nb<Q>(P, B.phi, c, a), phi, gr, lap);
   gr[0] *= 3.0f;
   gr[1] *= 3.0f;
   gr[2] *= 3.0f;
@@ -494,145 +863,114 @@ __global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T) {
 
   float h[Q], g[Q];
   load_node<Q, ST, ODD, true>(P, B, c, h, g);
-
-  const float phc = P.clamp ? fminf(fmaxf(phi, 0.0f), 1.0f) : phi;
-  const float rho = P.rho_l + phc * P.drho;  // Eq. density_interpolation
-  const float inv_rho = 1.0f / rho;
-  // chemical potential with the bulk term 4 beta phi (phi-1)(phi-1/2)
-  const float mu = P.beta4 * phi * (phi - 1.0f) * (phi - 0.5f) - P.kappa * lap;
-  const float fb = rho - P.fb_rhol;
-  float Fsb[3], grho[3];
-  Fsb[0] = mu * gr[0] + fb * P.gx;  // surface tension + body force
-  Fsb[1] = mu * gr[1] + fb * P.gy;
-  Fsb[2] = mu * gr[2] + fb * P.gz;
-  grho[0] = P.drho * gr[0];  // Eq. density_gradient_phase_field
-  grho[1] = P.drho * gr[1];
-  grho[2] = P.drho * gr[2];
-
-  // moments of g
   float p = 0.f, j[3] = {0.f, 0.f, 0.f};
   Stress S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int a = 0; a < Q; ++a) {
-    const float v = g[a];
-    p += v;
-    if (L::ex[a]) { j[0] += L::ex[a] * v; S.xx += v; }
-    if (L::ey[a]) { j[1] += L::ey[a] * v; S.yy += v; }
-    if (D == 3 && L::ez[a]) { j[2] += L::ez[a] * v; S.zz += v; }
-    if (L::ex[a] && L::ey[a]) S.xy += (L::ex[a] * L::ey[a]) * v;
-    if (D == 3 && L::ey[a] && L::ez[a]) S.yz += (L::ey[a] * L::ez[a]) * v;
-    if (D == 3 && L::ex[a] && L::ez[a]) S.xz += (L::ex[a] * L::ez[a]) * v;
-  }
-  const float tau = P.tau_l + phc * P.dtau;  // Eq. relaxation_time
-  const float s = 1.0f / (tau + 0.5f);
-
-  // macroscopic update: viscous force with the stored velocity
+  for (int a = 0; a < Q; ++a) add_moments<Q>(a, g[a], p, j, S);
   float up[3];
   up[0] = B.u[node];
   up[1] = B.u[N + node];
   up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
-  float Fm[3];
-  viscous_force<D>(S, p, up, tau, s, grho, Fm);
-  const float p3 = p * (1.0f / 3.0f);
-  float u[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float F = Fsb[d] - p3 * grho[d] + Fm[d];  // Eqs. total_force, pressure_force
-    u[d] = j[d] + 0.5f * F * inv_rho;               // Eq. velocity_update
-  }
-  if (D == 2) u[2] = 0.0f;
-  B.u[node] = u[0];
-  B.u[N + node] = u[1];
-  if (D == 3) B.u[2 * N + node] = u[2];
-  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  NodeCtx X;
+  macro<Q>(P, phi, gr, lap, p, j, S, up, X);
+  B.u[node] = X.u[0];
+  B.u[N + node] = X.u[1];
+  if (D == 3) B.u[2 * N + node] = X.u[2];
 
-  // phase-field collision (Eqs. lbe_interface, forcing_term, equilibrium_with_force)
-  {
-    const float theta = (1.0f - 4.0f * (phi - 0.5f) * (phi - 0.5f)) * P.inv_xi;
-    const float nrm = rsqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + 1e-24f);
-    const float tn[3] = {theta * gr[0] * nrm, theta * gr[1] * nrm, theta * gr[2] * nrm};
-    const float om = P.omega_h;
-    float pre_hi, pre_lo;
-    kahan_sum<Q>(h, pre_hi, pre_lo);
+  Ty* Gw = (Ty*)B.g;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const float w = L::w[a];
-      const float eu = L::ex[a] * u[0] + L::ey[a] * u[1] + L::ez[a] * u[2];
-      // h^eq = phi Gamma_a with phi = sum_a h_a carried as pre_hi + pre_lo
-      const float Ga = w * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
-      const float heq = fmaf(pre_hi, Ga, pre_lo * Ga);
-      const float fphi = w * (L::ex[a] * tn[0] + L::ey[a] * tn[1] + L::ez[a] * tn[2]);
-      h[a] = h[a] - om * (h[a] - heq + 0.5f * fphi) + fphi;
-    }
-    // The collision conserves sum_a h_a exactly (sum Gamma_a = 1, sum F^phi_a
-    // = 0), but the FP32 weights sum to 1 + O(1e-8), which would add a
-    // systematic mass drift each step; restore the node's mass with
-    // compensated sums (a zero correction in exact arithmetic).
-    float post_hi, post_lo;
-    kahan_sum<Q>(h, post_hi, post_lo);
-    h[0] += (pre_hi - post_hi) + (pre_lo - post_lo);
-    Ty* __restrict__ H = (Ty*)B.h;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      int sp, sn;
-      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_h(H, (size_t)sp * N + sn, h[a], 1.0f / L::w[a], phi);
-    }
+  for (int a = 0; a < Q; ++a) {
+    int sp, sn;
+    if (resolve_dst<Q, ODD>(P, c, a, sp, sn))
+      C::template st_g<NT>(Gw, (size_t)sp * N + sn, g_post<Q>(X, a), 1.0f / L::w[a]);
   }
+  float pre_s = 0.f, pre_c = 0.f, post_s = 0.f, post_c = 0.f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    kahan_add(h[a], pre_s, pre_c);
+    h[a] = h_post<Q>(X, a, h[a]);
+    kahan_add(h[a], post_s, post_c);
+  }
+  h[0] += (pre_s - post_s) - (pre_c - post_c);
+  Ty* Hw = (Ty*)B.h;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    int sp, sn;
+    if (!resolve_dst<Q, ODD>(P, c, a, sp, sn)) continue;
+    float ref = 0.0f;
+    if (ST != 0) {  // encode relative to the reader's phase field
+      int tn;
+      stream_target<Q>(P, c, a, tn);
+      ref = B.phi[tn];
+    }
+    C::template st_h<NT>(Hw, (size_t)sp * N + sn, h[a], 1.0f / L::w[a], ref);
+  }
+}
 
-  // hydrodynamic collision: WMRT with the viscous force re-evaluated at u^n
-  {
-    float Fc[3];
-    viscous_force<D>(S, p, u, tau, s, grho, Fc);
-    float F[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) F[d] = Fsb[d] - p3 * grho[d] + Fc[d];
-    // deviatoric second moments of g - fbar: dev(S - u u)
-    const float dxx = S.xx - u[0] * u[0], dyy = S.yy - u[1] * u[1];
-    const float dzz = (D == 3) ? S.zz - u[2] * u[2] : 0.0f;
-    const float dxy = S.xy - u[0] * u[1];
-    const float dyz = (D == 3) ? S.yz - u[1] * u[2] : 0.0f;
-    const float dxz = (D == 3) ? S.xz - u[0] * u[2] : 0.0f;
-    const float one_s = 1.0f - s;
-    const float f3r = 3.0f * inv_rho;
-    Ty* __restrict__ G = (Ty*)B.g;
-    float cxx, cyy, czz, cxy, cyz, cxz;  // projection coefficients times (1 - s)
-    if (D == 3) {
-      // weighted basis: P y = 4.5 w_a (e e : dev)
-      const float tr = (dxx + dyy + dzz) * (1.0f / 3.0f);
-      cxx = 4.5f * one_s * (dxx - tr);
-      cyy = 4.5f * one_s * (dyy - tr);
-      czz = 4.5f * one_s * (dzz - tr);
-      cxy = 9.0f * one_s * dxy;
-      cyz = 9.0f * one_s * dyz;
-      cxz = 9.0f * one_s * dxz;
-    } else {
-      // plain orthogonal D2Q9 basis: P y = [(ex^2-ey^2)(dxx-dyy) + ex ey dxy] / 4
-      cxx = 0.25f * one_s * (dxx - dyy);
-      cyy = -cxx;
-      czz = 0.0f;
-      cxy = 0.25f * one_s * dxy;
-      cyz = cxz = 0.0f;
-    }
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
-      const float w = L::w[a];
-      const float eu = ex * u[0] + ey * u[1] + ez * u[2];
-      const float feq = w * (p + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
-      const float Fa = w * f3r * (ex * F[0] + ey * F[1] + ez * F[2]);
-      float proj = 0.0f;
-      if (ex) proj += cxx;
-      if (ey) proj += cyy;
-      if (ez) proj += czz;
-      if (ex && ey) proj += (ex * ey) * cxy;
-      if (ey && ez) proj += (ey * ez) * cyz;
-      if (ex && ez) proj += (ex * ez) * cxz;
-      if (D == 3) proj *= w;
-      const float gp = feq + 0.5f * Fa + proj;
-      int sp, sn;
-      if (resolve_dst<Q, ODD>(P, c, a, sp, sn)) C::st_g(G, (size_t)sp * N + sn, gp, 1.0f / w);
-    }
+// Interior box: every axis whose faces are not periodic loses its two face
+// layers; the tiling covers the box.
+struct Box {
+  int x0, y0, z0, nx, ny, nz;  // origin and extent
+};
+
+__device__ __forceinline__ bool box_coords(const Box& X, const Tiling& T, int c[3]) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = L % T.ntx;
+  const int r = L / T.ntx;
+  const int ty = r % T.nty;
+  const int lx = tx * T.bx + (int)threadIdx.x % T.bx;
+  const int ly = ty * T.by + (int)threadIdx.x / T.bx;
+  c[0] = X.x0 + lx;
+  c[1] = X.y0 + ly;
+  c[2] = X.z0 + r / T.nty;
+  return lx < X.nx && ly < X.ny;
+}
+
+template <int Q, int ST, int ODD, bool NT>
+__global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T, Box X) {
+  int c[3];
+  if (!box_coords(X, T, c)) return;
+  step_fast<Q, ST, ODD, NT>(P, B, c);
+}
+
+// Face layers of non-periodic axes, enumerated slab by slab without overlap:
+// axis 0 faces (whole y-z planes), then axis 1 faces inside the x range left,
+// then axis 2 faces inside the x-y range left.
+struct Faces {
+  int n0, n1, n2;          // nodes in each slab (0 if the axis is periodic)
+  int x0, nxi, y0, nyi;    // interior x / y ranges used by later slabs
+};
+
+__device__ __forceinline__ void face_coords(const KParams& P, const Faces& F, int t, int c[3]) {
+  if (t < F.n0) {  // x = 0 or nx-1, all y, z
+    const int side = t & 1, r = t >> 1;
+    c[0] = side ? P.nx - 1 : 0;
+    c[1] = r % P.ny;
+    c[2] = r / P.ny;
+    return;
   }
+  t -= F.n0;
+  if (t < F.n1) {  // y = 0 or ny-1
+    const int side = t & 1, r = t >> 1;
+    c[1] = side ? P.ny - 1 : 0;
+    c[0] = F.x0 + r % F.nxi;
+    c[2] = r / F.nxi;
+    return;
+  }
+  t -= F.n1;  // z = 0 or nz-1
+  const int side = t & 1, r = t >> 1;
+  c[2] = side ? P.nz - 1 : 0;
+  c[0] = F.x0 + r % F.nxi;
+  c[1] = F.y0 + r / F.nxi;
+}
+
+template <int Q, int ST, int ODD, bool NT>
+__global__ __launch_bounds__(256) void k_step_faces(KParams P, KBufs B, Faces F) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F.n0 + F.n1 + F.n2) return;
+  int c[3];
+  face_coords(P, F, t, c);
+  step_general<Q, ST, ODD, NT>(P, B, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
 // ---------------------------------------------------------------------------
 
 // canonical (even-parity) initial populations from phi0, u0; the 16-bit
-// reference is phi0.
+// reference of a canonical slot is phi0 of its own node (its reader).
 template <int Q, int ST>
 __global__ __launch_bounds__(256) void k_init(KParams P, KBufs B, const float* __restrict__ phi0,
                                               const float* __restrict__ u0, Tiling T) {
@@ -724,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_init(KParams P, KBufs B, const float* _
     }
     int sp, sn, src;
     if (resolve_src<Q, 0>(P, c, a, sp, sn, src)) {
-      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : phi0[src]);
+      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : phi);
       C::st_g((Ty*)B.g, (size_t)sp * N + sn, gv, 1.0f / w);
     }
   }
@@ -784,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_import(KParams P, KBufs B, const float*
     int sp, sn, src;
     if (resolve_src<Q, 0>(P, c, a, sp, sn, src)) {
       const float w = Lat<Q>::w[a];
-      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : B.ref[src]);
+      C::st_h((Ty*)B.h, (size_t)sp * N + sn, hv, 1.0f / w, (ST == 0) ? 0.0f : B.ref[node]);
       C::st_g((Ty*)B.g, (size_t)sp * N + sn, gv, 1.0f / w);
     }
   }

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "kernels.hpp"
@@ -159,6 +161,45 @@ Tiling tiling_of(const lbm_params& p, int bx, int by) {
   return T;
 }
 
+bool axis_periodic(const lbm_params& p, int d) {
+  const int ndim = p.lattice == LBM_D2Q9 ? 2 : 3;
+  return d >= ndim || p.bc[2 * d] == LBM_BC_PERIODIC;
+}
+
+// interior box of the fused kernel and the face slabs around it
+void split_domain(const lbm_params& p, Box& X, Faces& F) {
+  const int n[3] = {p.nx, p.ny, p.nz};
+  int o[3], e[3];
+  for (int d = 0; d < 3; ++d) {
+    const bool per = axis_periodic(p, d);
+    o[d] = per ? 0 : 1;
+    e[d] = per ? n[d] : std::max(0, n[d] - 2);
+  }
+  X.x0 = o[0];
+  X.y0 = o[1];
+  X.z0 = o[2];
+  X.nx = e[0];
+  X.ny = e[1];
+  X.nz = e[2];
+  F.n0 = axis_periodic(p, 0) ? 0 : 2 * p.ny * p.nz;
+  F.x0 = o[0];
+  F.nxi = e[0];
+  F.n1 = axis_periodic(p, 1) ? 0 : 2 * e[0] * p.nz;
+  F.y0 = o[1];
+  F.nyi = e[1];
+  F.n2 = axis_periodic(p, 2) ? 0 : 2 * e[0] * e[1];
+}
+
+Tiling box_tiling(const Box& X, int bx, int by) {
+  Tiling T;
+  T.bx = bx;
+  T.by = by;
+  T.ntx = (X.nx + bx - 1) / bx;
+  T.nty = (X.ny + by - 1) / by;
+  T.ntiles = (X.nx > 0 && X.ny > 0) ? T.ntx * T.nty * X.nz : 0;
+  return T;
+}
+
 void default_tile(const lbm_params& p, int& bx, int& by) {
   if (p.nx >= 64 && p.nx % 64 == 0) {
     bx = 64;
@@ -177,7 +218,10 @@ void default_tile(const lbm_params& p, int& bx, int& by) {
 struct lbm_sim {
   lbm_params P;
   KParams K;
-  Tiling T;
+  Tiling T;             // whole domain (phi pass and auxiliary kernels)
+  Tiling TB;            // interior box of the fused kernel
+  Box box;
+  Faces faces;
   Layout L;
   int Q, ST;
   size_t N;
@@ -192,6 +236,7 @@ struct lbm_sim {
   hipGraphExec_t g_pair, g_many;
   int many_pairs;
   bool graphs_ok;
+  bool nt;              // non-temporal population stores in the fused kernel
   float* phi(int i) { return (float*)(base + (i == 0 ? L.phi0 : L.phi1)); }
   void* h() { return base + L.h; }
   void* g() { return base + L.g; }
@@ -230,10 +275,36 @@ hipError_t launch_step_t(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
   else
     hipLaunchKernelGGL((k_phi<Q, ST, 1>), grid, block, 0, st, K, B, T);
   if (ev) (void)hipEventRecord(ev[1], st);
-  if (par == 0)
-    hipLaunchKernelGGL((k_step<Q, ST, 0>), grid, block, 0, st, K, B, T);
-  else
-    hipLaunchKernelGGL((k_step<Q, ST, 1>), grid, block, 0, st, K, B, T);
+  const Tiling& TB = s->TB;
+  if (TB.ntiles > 0) {
+    const dim3 gb(TB.ntiles);
+    if (s->nt) {
+      if (par == 0)
+        hipLaunchKernelGGL((k_step<Q, ST, 0, true>), gb, block, 0, st, K, B, TB, s->box);
+      else
+        hipLaunchKernelGGL((k_step<Q, ST, 1, true>), gb, block, 0, st, K, B, TB, s->box);
+    } else {
+      if (par == 0)
+        hipLaunchKernelGGL((k_step<Q, ST, 0, false>), gb, block, 0, st, K, B, TB, s->box);
+      else
+        hipLaunchKernelGGL((k_step<Q, ST, 1, false>), gb, block, 0, st, K, B, TB, s->box);
+    }
+  }
+  const int nface = s->faces.n0 + s->faces.n1 + s->faces.n2;
+  if (nface > 0) {
+    const dim3 gf((nface + 255) / 256), bf(256);
+    if (s->nt) {
+      if (par == 0)
+        hipLaunchKernelGGL((k_step_faces<Q, ST, 0, true>), gf, bf, 0, st, K, B, s->faces);
+      else
+        hipLaunchKernelGGL((k_step_faces<Q, ST, 1, true>), gf, bf, 0, st, K, B, s->faces);
+    } else {
+      if (par == 0)
+        hipLaunchKernelGGL((k_step_faces<Q, ST, 0, false>), gf, bf, 0, st, K, B, s->faces);
+      else
+        hipLaunchKernelGGL((k_step_faces<Q, ST, 1, false>), gf, bf, 0, st, K, B, s->faces);
+    }
+  }
   if (ev) (void)hipEventRecord(ev[2], st);
   if (K.has_outlet) {
     KBufs Bo = B;
@@ -411,9 +482,12 @@ int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, vo
   s->steps = 0;
   s->g_pair = s->g_many = nullptr;
   s->graphs_ok = false;
+  s->nt = false;
   int bx, by;
   default_tile(*p, bx, by);
+  split_domain(*p, s->box, s->faces);
   s->T = tiling_of(*p, bx, by);
+  s->TB = box_tiling(s->box, bx, by);
   s->nparts = 1024;
   hipError_t e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&s->part, sizeof(double) * 2 * s->nparts);
@@ -550,6 +624,14 @@ int lbm_set_tile(lbm_sim* s, int bx, int by) {
   if (bx < 16 || bx % 16 || by < 1 || (t != 64 && t != 128 && t != 256 && t != 512))
     return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by in {64,128,256,512}");
   s->T = tiling_of(s->P, bx, by);
+  s->TB = box_tiling(s->box, bx, by);
+  drop_graphs(s);
+  return LBM_OK;
+}
+
+int lbm_set_store_hint(lbm_sim* s, int nontemporal) {
+  if (!s) return fail(LBM_EINVAL, "null handle");
+  s->nt = nontemporal != 0;
   drop_graphs(s);
   return LBM_OK;
 }
@@ -596,6 +678,93 @@ int lbm_kernel_times(lbm_sim* s, int n, double* out_ms) {
   for (int i = 0; i < K * batch; ++i) hipEventDestroy(ev[i]);
   if (rc) return rc;
   for (int k = 0; k < 3; ++k) out_ms[k] = acc[k] / n;
+  return LBM_OK;
+}
+
+namespace {
+struct TuneEntry {
+  int bx, by, nt;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune_cache;
+
+std::string tune_key(const lbm_sim* s) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "q%d st%d %dx%dx%d bc%d%d%d%d%d%d o%d i%d", s->Q, s->ST, s->P.nx, s->P.ny, s->P.nz,
+           s->P.bc[0], s->P.bc[1], s->P.bc[2], s->P.bc[3], s->P.bc[4], s->P.bc[5], s->K.has_outlet,
+           s->K.has_inlet);
+  return buf;
+}
+
+// mean ms per eager step over n steps (events around the whole step)
+int time_steps(lbm_sim* s, int n, double* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s->stream));
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = launch_step(s, s->parity(), s->stream);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(LBM_EDEVICE, hipGetErrorString(e));
+    }
+    s->steps += 1;
+  }
+  HIPCHK(hipEventRecord(e1, s->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = t / n;
+  return LBM_OK;
+}
+}  // namespace
+
+int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_out, double* ms_out) {
+  if (!s || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
+  const std::string key = tune_key(s);
+  TuneEntry best = {s->T.bx, s->T.by, s->nt ? 1 : 0, 1e30};
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    static const int cand[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4},
+                                  {256, 2}, {32, 16}, {64, 2}, {128, 1}, {32, 4}, {16, 16}};
+    for (const auto& cb : cand) {
+      const int bx = cb[0], by = cb[1];
+      if (bx > 16 && bx >= 2 * s->P.nx) continue;  // mostly idle lanes
+      if (by > 1 && by > s->P.ny) continue;
+      for (int nt = 0; nt < 2; ++nt) {
+        s->T = tiling_of(s->P, bx, by);
+        s->TB = box_tiling(s->box, bx, by);
+        s->nt = nt != 0;
+        double ms = 0.0;
+        int rc = time_steps(s, 2, &ms);  // warm-up
+        if (rc == LBM_OK) rc = time_steps(s, trial_steps, &ms);
+        if (rc) return rc;
+        if (ms < best.ms) best = {bx, by, nt, ms};
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  s->T = tiling_of(s->P, best.bx, best.by);
+  s->TB = box_tiling(s->box, best.bx, best.by);
+  s->nt = best.nt != 0;
+  drop_graphs(s);
+  if (bx_out) *bx_out = best.bx;
+  if (by_out) *by_out = best.by;
+  if (nt_out) *nt_out = best.nt;
+  if (ms_out) *ms_out = best.ms;
   return LBM_OK;
 }
 

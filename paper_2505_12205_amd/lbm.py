@@ -64,6 +64,9 @@ def _load():
     L.lbm_set_tile.argtypes = [vp, C.c_int, C.c_int]
     L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
+    L.lbm_set_store_hint.argtypes = [vp, C.c_int]
+    L.lbm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_version.restype = C.c_char_p
@@ -74,8 +77,8 @@ lib = _load()
 
 EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fields", "lbm_reduce",
             "lbm_export_state", "lbm_import_state", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
-            "lbm_set_tile", "lbm_get_tile", "lbm_kernel_times", "lbm_destroy", "lbm_last_error",
-            "lbm_version")
+            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_autotune",
+            "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version")
 
 
 def _check(rc):
@@ -223,6 +226,18 @@ class Sim:
         bx, by = C.c_int(), C.c_int()
         _check(lib.lbm_get_tile(self._h, C.byref(bx), C.byref(by)))
         return bx.value, by.value
+
+    def set_store_hint(self, nontemporal: bool):
+        _check(lib.lbm_set_store_hint(self._h, 1 if nontemporal else 0))
+        return self
+
+    def autotune(self, trial_steps: int = 10):
+        """Pick the fastest tile shape and store hint (cached per shape); returns
+        (bx, by, nontemporal, ms_per_step).  Advances the state by the trials."""
+        bx, by, nt, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        _check(lib.lbm_autotune(self._h, int(trial_steps), C.byref(bx), C.byref(by), C.byref(nt),
+                                C.byref(ms)))
+        return bx.value, by.value, bool(nt.value), ms.value
 
     def kernel_times(self, n: int):
         """Mean ms of (phase-field pass, fused step kernel, boundary planes) over n eager steps."""
