@@ -52,6 +52,31 @@ def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True):
     return sim, dt, kt, mass, ke
 
 
+def run_batch(steps, warmup, storage="fp16", autotune=True):
+    """The batched Weber sweep: 64 jet domains 96 x 96 x L_k (seeded lengths
+    256..768), We_k log-spaced 0.5..8, one set of launches per step."""
+    import torch
+
+    from paper_2505_12205_amd import lbm
+    from paper_2505_12205_amd import workloads as W
+    doms = W.jet_sweep()
+    bt = lbm.Batch(doms, storage=storage)
+    del doms
+    if autotune:
+        choice = bt.autotune(trial_steps=4)
+        print(f"[bench] batch {storage} autotune -> tile {choice[0]}x{choice[1]} blocks/CU={choice[2]} "
+              f"nontemporal={choice[3]} {choice[4]:.3f} ms/step", file=sys.stderr, flush=True)
+    bt.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = bt.kernel_times(6)
+    lb = bt.intact_length(0.5)
+    return bt.nodes, dt, kt, lb
+
+
 def copy_probe(gib: float = 2.0, reps: int = 10):
     """Device-to-device copy of a buffer of known size (torch's copy kernel):
     the practical HBM ceiling, and the calibration run for the byte counters."""
@@ -101,6 +126,7 @@ def main():
                     help="comma list of 16-bit storage forms to time beside FP32 ('' for none)")
     ap.add_argument("--tile", default="", help="bx,by launch shape of the fused kernel")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched Weber sweep")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -146,6 +172,17 @@ def main():
                      "step_kernel_GBs": round(bk2 * N / (kt2[1] * 1e-3) / 1e9, 1)}
         print(f"[bench] {st} {forms[st]}", file=sys.stderr, flush=True)
         del s2
+        torch.cuda.empty_cache()
+
+    if not args.no_batch:
+        nb, dtb, ktb, lb = run_batch(max(20, args.steps // 4), 4, "fp16", not args.no_autotune)
+        nsb = max(20, args.steps // 4)
+        forms["batched_fp16"] = {"MLUPS": round(nb * nsb / dtb / 1e6, 1), "domains": 64, "nodes": nb,
+                                 "ms_per_step": round(dtb / nsb * 1e3, 3),
+                                 "phi_ms": round(ktb[0], 3), "step_ms": round(ktb[1], 3),
+                                 "outlet_ms": round(ktb[2], 4),
+                                 "intact_length_range": [min(lb), max(lb)]}
+        print(f"[bench] batched_fp16 {forms['batched_fp16']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
     out = {

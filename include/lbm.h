@@ -171,6 +171,49 @@ void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(void);
 const char* lbm_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batched form: ndom independent domains (each with its own lbm_params and
+ * initial fields; all share the lattice and the storage form) advanced by
+ * the same kernel launches.  Per step: one persistent launch walks the
+ * interior tiles of all domains in contiguous chunks for the phase-field
+ * pass, one for the fused step, plus one launch over the face layers of all
+ * domains for each, and one over all outlet planes.  Pairs of steps replay a
+ * captured hipGraph.  Every domain's arithmetic is the single-domain
+ * arithmetic, node for node.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* Bytes of the caller-owned arena for all domains (each slice 256-B aligned). */
+int lbm_batch_state_bytes(int ndom, const lbm_params* per_domain, size_t* bytes);
+
+/* phi0_dev[d] (required) and u0_dev[d] (u0_dev or its entries may be NULL)
+ * are device pointers to each domain's initial fields, read before return
+ * of the init kernels on `stream` (keep them alive until the stream has run
+ * them).  state_dev: caller-allocated arena of lbm_batch_state_bytes(). */
+int lbm_batch_init(int ndom, const lbm_params* per_domain, const float* const* phi0_dev,
+                   const float* const* u0_dev, void* state_dev, size_t state_bytes, void* stream,
+                   lbm_batch** out);
+int lbm_batch_step(lbm_batch* b, int n);
+long long lbm_batch_steps_done(const lbm_batch* b);
+/* mass[ndom], kinetic[ndom] (host); FP64, fixed order; synchronises */
+int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic);
+int lbm_batch_fields(lbm_batch* b, int dom, unsigned mask, float* phi_dev, float* u_dev, float* p_dev);
+int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, float* u_dev);
+/* Intact liquid length of each domain, length[ndom] (host), in nodes along
+ * the streamwise axis: the first layer from the inlet with no node above
+ * `threshold` (the layer count if none).  Synchronises. */
+int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length);
+/* launch shape: threads per block bx*by (as lbm_set_tile), resident blocks
+ * per compute unit of the persistent launches, non-temporal stores */
+int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal);
+/* autotuner over tile shape x blocks per CU x store hint; cached per batch
+ * shape for the process; advances the state by the trials; synchronises */
+int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blocks_per_cu,
+                       int* nontemporal, double* ms_per_step);
+/* mean ms of (phase-field launches, fused-step launches, outlet launch) */
+int lbm_batch_kernel_times(lbm_batch* b, int n, double* out_ms);
+void lbm_batch_destroy(lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -476,25 +476,9 @@ __device__ __forceinline__ void kahan_sum(const float* v, float& hi, float& lo) 
 }
 
 // ---------------------------------------------------------------------------
-// k_phi: phase field of the current state
+// k_phi: phase field of the current state (defined after the neighbour
+// helpers below)
 // ---------------------------------------------------------------------------
-template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T) {
-  int c[3];
-  if (!tile_coords(P, T, c)) return;
-  const int node = node_of(P, c[0], c[1], c[2]);
-  float phi;
-  if (is_inlet_node<Q>(P, c)) {
-    float p0, p1;
-    inlet_tangential<Q>(c, p0, p1);
-    phi = inlet_psi(P, p0, p1);  // sum_a h_a = phi_in exactly after the inlet condition
-  } else {
-    float h[Q], g[1], lo;
-    load_node<Q, ST, ODD, false>(P, B, c, h, g);
-    kahan_sum<Q>(h, phi, lo);
-  }
-  B.phi_out[node] = phi;
-}
 
 // ---------------------------------------------------------------------------
 // node physics (shared by the fast interior path and the general path)
@@ -913,17 +897,21 @@ struct Box {
   int x0, y0, z0, nx, ny, nz;  // origin and extent
 };
 
-__device__ __forceinline__ bool box_coords(const Box& X, const Tiling& T, int c[3]) {
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+// node of thread tid in tile L of the box (x fastest, then y, then z)
+__device__ __forceinline__ bool tile_node(const Box& X, const Tiling& T, int L, int tid, int c[3]) {
   const int tx = L % T.ntx;
   const int r = L / T.ntx;
   const int ty = r % T.nty;
-  const int lx = tx * T.bx + (int)threadIdx.x % T.bx;
-  const int ly = ty * T.by + (int)threadIdx.x / T.bx;
+  const int lx = tx * T.bx + tid % T.bx;
+  const int ly = ty * T.by + tid / T.bx;
   c[0] = X.x0 + lx;
   c[1] = X.y0 + ly;
   c[2] = X.z0 + r / T.nty;
   return lx < X.nx && ly < X.ny;
+}
+
+__device__ __forceinline__ bool box_coords(const Box& X, const Tiling& T, int c[3]) {
+  return tile_node(X, T, xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x, c);
 }
 
 template <int Q, int ST, int ODD, bool NT>
@@ -974,13 +962,68 @@ __global__ __launch_bounds__(256) void k_step_faces(KParams P, KBufs B, Faces F)
 }
 
 // ---------------------------------------------------------------------------
+// k_phi: phase field phi = sum_a h_a of the current state (Eq.
+// phase_field_variable), compensated sum; interior box and face layers
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int ODD>
+__device__ __forceinline__ void phi_fast(const KParams& P, const KBufs& B, const int c[3]) {
+  using L = Lat<Q>;
+  using C = Codec<ST>;
+  using Ty = typename C::T;
+  const Nbr nb = make_nbr(P, c);
+  const int node = nb.node;
+  const size_t NN = (size_t)P.N;
+  const Ty* Hp = (const Ty*)B.h;
+  const float ref = (ST == 0) ? 0.0f : B.ref[node];
+  float s = 0.0f, cc = 0.0f;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int pop = ODD ? L::opp[a] : a;
+    const unsigned idx = ODD ? (unsigned)nb.at<Q>(L::opp[a]) : (unsigned)node;
+    kahan_add(C::ld_h(Hp + pop * NN, idx, L::w[a], ref), s, cc);
+  }
+  B.phi_out[node] = s - cc;
+}
+
+template <int Q, int ST, int ODD>
+__device__ __forceinline__ void phi_general(const KParams& P, const KBufs& B, const int c[3]) {
+  const int node = node_of(P, c[0], c[1], c[2]);
+  float phi;
+  if (is_inlet_node<Q>(P, c)) {
+    float p0, p1;
+    inlet_tangential<Q>(c, p0, p1);
+    phi = inlet_psi(P, p0, p1);  // sum_a h_a = phi_in exactly after the inlet condition
+  } else {
+    float h[Q], g[1], lo;
+    load_node<Q, ST, ODD, false>(P, B, c, h, g);
+    kahan_sum<Q>(h, phi, lo);
+    phi += lo;
+  }
+  B.phi_out[node] = phi;
+}
+
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T, Box X) {
+  int c[3];
+  if (!box_coords(X, T, c)) return;
+  phi_fast<Q, ST, ODD>(P, B, c);
+}
+
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void k_phi_faces(KParams P, KBufs B, Faces F) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F.n0 + F.n1 + F.n2) return;
+  int c[3];
+  face_coords(P, F, t, c);
+  phi_general<Q, ST, ODD>(P, B, c);
+}
+
+// ---------------------------------------------------------------------------
 // k_outlet: convective outflow (appendix B) after the step of parity ODD
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
+__device__ __forceinline__ void outlet_node(const KParams& P, const KBufs& B, int pi) {
   constexpr int AX = Lat<Q>::AX;
-  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pi >= P.plane) return;
   int c[3];
   if (Lat<Q>::D == 3) {
     c[0] = pi % P.nx;
@@ -1004,6 +1047,108 @@ __global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
     *oh = (*oh + U * h[a]) * inv;
     *og = (*og + U * g[a]) * inv;
   }
+}
+
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= P.plane) return;
+  outlet_node<Q, ST, ODD>(P, B, pi);
+}
+
+// ---------------------------------------------------------------------------
+// batched form: many domains (own parameters, own buffers) per launch
+// ---------------------------------------------------------------------------
+struct DomDev {
+  KParams K;
+  KBufs B[2];   // buffers of a step of parity 0 / 1
+  KBufs Bo[2];  // buffers of the outlet update after a step of parity 0 / 1
+  Box X;
+  Faces F;
+  int ntx, nty, ntiles;     // interior tiling
+  int tile_base, face_base, plane_base;
+};
+
+// Persistent, chunked launch over the tile list of all domains: each block
+// walks a contiguous chunk of tiles (contiguous per XCD after the remap), so
+// neighbouring tiles of one domain share an L2.
+template <int Q, int ST, int ODD, bool NT, bool PHI>
+__global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D, const int* __restrict__ tile_dom,
+                                                   int ntiles, int chunk, int bx, int by) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int t0 = L * chunk;
+  const int t1 = min(t0 + chunk, ntiles);
+  for (int t = t0; t < t1; ++t) {
+    const int d = tile_dom[t];
+    const DomDev& dm = D[d];
+    Tiling T;
+    T.bx = bx;
+    T.by = by;
+    T.ntx = dm.ntx;
+    T.nty = dm.nty;
+    T.ntiles = dm.ntiles;
+    int c[3];
+    if (!tile_node(dm.X, T, t - dm.tile_base, (int)threadIdx.x, c)) continue;
+    if (PHI)
+      phi_fast<Q, ST, ODD>(dm.K, dm.B[ODD], c);
+    else
+      step_fast<Q, ST, ODD, NT>(dm.K, dm.B[ODD], c);
+  }
+}
+
+// domain of flat index t given per-domain bases (ascending)
+template <int WHICH>
+__device__ __forceinline__ int find_dom(const DomDev* __restrict__ D, int ndom, int t) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int base = WHICH == 0 ? D[mid].face_base : D[mid].plane_base;
+    if (base <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int Q, int ST, int ODD, bool NT, bool PHI>
+__global__ __launch_bounds__(256) void kb_faces(const DomDev* __restrict__ D, int ndom, int nface) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nface) return;
+  const int d = find_dom<0>(D, ndom, t);
+  const DomDev& dm = D[d];
+  int c[3];
+  face_coords(dm.K, dm.F, t - dm.face_base, c);
+  if (PHI)
+    phi_general<Q, ST, ODD>(dm.K, dm.B[ODD], c);
+  else
+    step_general<Q, ST, ODD, NT>(dm.K, dm.B[ODD], c);
+}
+
+template <int Q, int ST, int ODD>
+__global__ __launch_bounds__(256) void kb_outlet(const DomDev* __restrict__ D, int ndom, int nplane) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nplane) return;
+  const int d = find_dom<1>(D, ndom, t);
+  const DomDev& dm = D[d];
+  if (!dm.K.has_outlet) return;
+  outlet_node<Q, ST, ODD>(dm.K, dm.Bo[ODD], t - dm.plane_base);
+}
+
+// per-plane count of nodes with phi > threshold along the streamwise axis
+// (one block per plane); used for the intact-length diagnostic
+__global__ __launch_bounds__(256) void k_plane_count(const float* __restrict__ phi, int plane, int nplanes,
+                                                     float thr, int* __restrict__ count) {
+  __shared__ int sc[256];
+  const int z = blockIdx.x;
+  if (z >= nplanes) return;
+  int n = 0;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) n += phi[(size_t)z * plane + i] > thr ? 1 : 0;
+  sc[threadIdx.x] = n;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[z] = sc[0];
 }
 
 // ---------------------------------------------------------------------------

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "lbm.h"
@@ -264,16 +265,34 @@ namespace {
 
 // ---- template dispatch ----------------------------------------------------
 template <int Q, int ST>
+void launch_phi_kernels(lbm_sim* s, int par, hipStream_t st) {
+  KBufs B = s->bufs(par);
+  const Tiling& TB = s->TB;
+  const dim3 block(TB.bx * TB.by);
+  if (TB.ntiles > 0) {
+    if (par == 0)
+      hipLaunchKernelGGL((k_phi<Q, ST, 0>), dim3(TB.ntiles), block, 0, st, s->K, B, TB, s->box);
+    else
+      hipLaunchKernelGGL((k_phi<Q, ST, 1>), dim3(TB.ntiles), block, 0, st, s->K, B, TB, s->box);
+  }
+  const int nface = s->faces.n0 + s->faces.n1 + s->faces.n2;
+  if (nface > 0) {
+    const dim3 gf((nface + 255) / 256), bf(256);
+    if (par == 0)
+      hipLaunchKernelGGL((k_phi_faces<Q, ST, 0>), gf, bf, 0, st, s->K, B, s->faces);
+    else
+      hipLaunchKernelGGL((k_phi_faces<Q, ST, 1>), gf, bf, 0, st, s->K, B, s->faces);
+  }
+}
+
+template <int Q, int ST>
 hipError_t launch_step_t(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
   const KParams& K = s->K;
   const Tiling& T = s->T;
   const dim3 grid(T.ntiles), block(T.bx * T.by);
   KBufs B = s->bufs(par);
   if (ev) (void)hipEventRecord(ev[0], st);
-  if (par == 0)
-    hipLaunchKernelGGL((k_phi<Q, ST, 0>), grid, block, 0, st, K, B, T);
-  else
-    hipLaunchKernelGGL((k_phi<Q, ST, 1>), grid, block, 0, st, K, B, T);
+  launch_phi_kernels<Q, ST>(s, par, st);
   if (ev) (void)hipEventRecord(ev[1], st);
   const Tiling& TB = s->TB;
   if (TB.ntiles > 0) {
@@ -334,13 +353,7 @@ hipError_t launch_step(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev = nul
 
 template <int Q, int ST>
 hipError_t launch_phi_t(lbm_sim* s, hipStream_t st) {
-  const int par = s->parity();
-  KBufs B = s->bufs(par);
-  const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
-  if (par == 0)
-    hipLaunchKernelGGL((k_phi<Q, ST, 0>), grid, block, 0, st, s->K, B, s->T);
-  else
-    hipLaunchKernelGGL((k_phi<Q, ST, 1>), grid, block, 0, st, s->K, B, s->T);
+  launch_phi_kernels<Q, ST>(s, s->parity(), st);
   return hipGetLastError();
 }
 
@@ -462,27 +475,27 @@ int lbm_state_bytes(const lbm_params* p, size_t* bytes) {
   return LBM_OK;
 }
 
-int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, void* state_dev,
-             size_t state_bytes, void* stream, lbm_sim** out) {
-  int rc = validate(p);
-  if (rc) return rc;
-  if (!out || !phi0_dev || !state_dev) return fail(LBM_EINVAL, "null pointer argument");
-  const Layout L = layout_of(*p);
-  if (state_bytes < L.total) return fail(LBM_ENOMEM, "state buffer smaller than lbm_state_bytes()");
-  if (((uintptr_t)state_dev) & 255) return fail(LBM_EINVAL, "state buffer must be 256-byte aligned");
+}  // extern "C"
+
+namespace {
+
+// simulation object on an existing state buffer; no launch
+lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
   lbm_sim* s = new lbm_sim();
   s->P = *p;
   s->K = kparams_of(*p);
-  s->L = L;
+  s->L = layout_of(*p);
   s->Q = p->lattice;
   s->ST = p->storage;
   s->N = (size_t)p->nx * p->ny * p->nz;
-  s->base = (char*)state_dev;
-  s->stream = (hipStream_t)stream;
+  s->base = base;
+  s->stream = stream;
   s->steps = 0;
   s->g_pair = s->g_many = nullptr;
   s->graphs_ok = false;
   s->nt = false;
+  s->part = s->res = s->res_host = nullptr;
+  s->cap = nullptr;
   int bx, by;
   default_tile(*p, bx, by);
   split_domain(*p, s->box, s->faces);
@@ -494,21 +507,44 @@ int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, vo
   if (e == hipSuccess) e = hipMalloc(&s->res, sizeof(double) * 2);
   if (e == hipSuccess) e = hipHostMalloc(&s->res_host, sizeof(double) * 2, hipHostMallocDefault);
   if (e != hipSuccess) {
-    delete s;
-    return fail(LBM_ENOMEM, std::string("library scratch: ") + hipGetErrorString(e));
-  }
-  e = DISPATCH(launch_init_t, s, phi0_dev, u0_dev);
-  if (e != hipSuccess) {
+    *rc = fail(LBM_ENOMEM, std::string("library scratch: ") + hipGetErrorString(e));
     lbm_destroy(s);
-    return fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
+    return nullptr;
   }
-  // the 16-bit forms decode with the phase field of the encoding step: phi0
+  *rc = LBM_OK;
+  return s;
+}
+
+// initial populations (even-parity slots) from phi0, u0
+int init_kernels(lbm_sim* s, const float* phi0_dev, const float* u0_dev) {
+  hipError_t e = DISPATCH(launch_init_t, s, phi0_dev, u0_dev);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("init kernel: ") + hipGetErrorString(e));
+  // the 16-bit forms decode with the reader's phase field: phi0
   if (s->ST != LBM_FP32) {
     e = hipMemcpyAsync(s->ref_buf(0), phi0_dev, s->N * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
-    if (e != hipSuccess) {
-      lbm_destroy(s);
-      return fail(LBM_EDEVICE, std::string("init copy: ") + hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(LBM_EDEVICE, std::string("init copy: ") + hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, void* state_dev,
+             size_t state_bytes, void* stream, lbm_sim** out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out || !phi0_dev || !state_dev) return fail(LBM_EINVAL, "null pointer argument");
+  const Layout L = layout_of(*p);
+  if (state_bytes < L.total) return fail(LBM_ENOMEM, "state buffer smaller than lbm_state_bytes()");
+  if (((uintptr_t)state_dev) & 255) return fail(LBM_EINVAL, "state buffer must be 256-byte aligned");
+  lbm_sim* s = new_sim(p, (char*)state_dev, (hipStream_t)stream, &rc);
+  if (!s) return rc;
+  rc = init_kernels(s, phi0_dev, u0_dev);
+  if (rc) {
+    lbm_destroy(s);
+    return rc;
   }
   *out = s;
   return LBM_OK;
@@ -776,6 +812,450 @@ void lbm_destroy(lbm_sim* s) {
   if (s->res_host) hipHostFree(s->res_host);
   if (s->cap) hipStreamDestroy(s->cap);
   delete s;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent domains advanced by the same launches
+// ===========================================================================
+struct lbm_batch {
+  int ndom = 0, Q = 0, ST = 0;
+  std::vector<lbm_sim*> views;  // one per domain, on its slice of the arena
+  std::vector<size_t> off;
+  char* base = nullptr;
+  hipStream_t stream = nullptr, cap = nullptr;
+  DomDev* d_dom = nullptr;
+  int* d_tile_dom = nullptr;
+  int ntiles = 0, nface = 0, nplane = 0;
+  int bx = 32, by = 8, bpc = 4, nt = 0, grid = 0, chunk = 1;
+  long long steps = 0;
+  hipGraphExec_t g_pair = nullptr;
+  int* d_count = nullptr;
+  int count_cap = 0;
+};
+
+namespace {
+
+size_t batch_layout(int ndom, const lbm_params* p, std::vector<size_t>& off) {
+  off.resize(ndom);
+  size_t tot = 0;
+  for (int d = 0; d < ndom; ++d) {
+    off[d] = tot;
+    tot = align256(tot + layout_of(p[d]).total);
+  }
+  return tot;
+}
+
+int batch_validate(int ndom, const lbm_params* p) {
+  if (ndom < 1 || !p) return fail(LBM_EINVAL, "need at least one domain");
+  for (int d = 0; d < ndom; ++d) {
+    int rc = validate(&p[d]);
+    if (rc) return fail(rc, "domain " + std::to_string(d) + ": " + g_err);
+    if (p[d].lattice != p[0].lattice || p[d].storage != p[0].storage)
+      return fail(LBM_EINVAL, "all domains of a batch share lattice and storage");
+  }
+  return LBM_OK;
+}
+
+void batch_drop_graph(lbm_batch* b) {
+  if (b->g_pair) hipGraphExecDestroy(b->g_pair);
+  b->g_pair = nullptr;
+}
+
+int batch_tables(lbm_batch* b) {
+  std::vector<DomDev> dom(b->ndom);
+  std::vector<int> tile_dom;
+  int tb = 0, fb = 0, pb = 0;
+  for (int d = 0; d < b->ndom; ++d) {
+    lbm_sim* v = b->views[d];
+    v->T = tiling_of(v->P, b->bx, b->by);
+    v->TB = box_tiling(v->box, b->bx, b->by);
+    v->nt = b->nt != 0;
+    DomDev& m = dom[d];
+    memset(&m, 0, sizeof m);
+    m.K = v->K;
+    for (int par = 0; par < 2; ++par) {
+      m.B[par] = v->bufs(par);
+      m.Bo[par] = v->bufs(par);
+      m.Bo[par].ref = v->out_buf(par);
+    }
+    m.X = v->box;
+    m.F = v->faces;
+    m.ntx = v->TB.ntx;
+    m.nty = v->TB.nty;
+    m.ntiles = v->TB.ntiles;
+    m.tile_base = tb;
+    m.face_base = fb;
+    m.plane_base = pb;
+    for (int t = 0; t < v->TB.ntiles; ++t) tile_dom.push_back(d);
+    tb += v->TB.ntiles;
+    fb += v->faces.n0 + v->faces.n1 + v->faces.n2;
+    pb += v->K.has_outlet ? v->K.plane : 0;
+  }
+  b->ntiles = tb;
+  b->nface = fb;
+  b->nplane = pb;
+  if (b->d_dom) hipFree(b->d_dom);
+  if (b->d_tile_dom) hipFree(b->d_tile_dom);
+  b->d_dom = nullptr;
+  b->d_tile_dom = nullptr;
+  HIPCHK(hipMalloc(&b->d_dom, sizeof(DomDev) * b->ndom));
+  HIPCHK(hipMalloc(&b->d_tile_dom, sizeof(int) * std::max(1, tb)));
+  HIPCHK(hipMemcpy(b->d_dom, dom.data(), sizeof(DomDev) * b->ndom, hipMemcpyHostToDevice));
+  if (tb) HIPCHK(hipMemcpy(b->d_tile_dom, tile_dom.data(), sizeof(int) * tb, hipMemcpyHostToDevice));
+  int dev = 0, cus = 256;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  b->grid = std::max(1, std::min(tb, cus * b->bpc));
+  b->chunk = std::max(1, (tb + b->grid - 1) / b->grid);
+  b->grid = std::max(1, (tb + b->chunk - 1) / b->chunk);
+  batch_drop_graph(b);
+  return LBM_OK;
+}
+
+template <int Q, int ST>
+hipError_t batch_launch_t(lbm_batch* b, int par, hipStream_t st, hipEvent_t* ev) {
+  const dim3 gi(b->grid), bi(b->bx * b->by);
+  const dim3 gf((b->nface + 255) / 256), bf(256);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  if (b->ntiles) {
+    if (par == 0)
+      hipLaunchKernelGGL((kb_interior<Q, ST, 0, false, true>), gi, bi, 0, st, b->d_dom, b->d_tile_dom, b->ntiles,
+                         b->chunk, b->bx, b->by);
+    else
+      hipLaunchKernelGGL((kb_interior<Q, ST, 1, false, true>), gi, bi, 0, st, b->d_dom, b->d_tile_dom, b->ntiles,
+                         b->chunk, b->bx, b->by);
+  }
+  if (b->nface) {
+    if (par == 0)
+      hipLaunchKernelGGL((kb_faces<Q, ST, 0, false, true>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);
+    else
+      hipLaunchKernelGGL((kb_faces<Q, ST, 1, false, true>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);
+  }
+  if (ev) (void)hipEventRecord(ev[1], st);
+#define KB_STEP(PAR, NTV)                                                                                  \
+  do {                                                                                                     \
+    if (b->ntiles)                                                                                         \
+      hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NTV, false>), gi, bi, 0, st, b->d_dom, b->d_tile_dom,    \
+                         b->ntiles, b->chunk, b->bx, b->by);                                               \
+    if (b->nface)                                                                                          \
+      hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NTV, false>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);  \
+  } while (0)
+  if (par == 0) {
+    if (b->nt)
+      KB_STEP(0, true);
+    else
+      KB_STEP(0, false);
+  } else {
+    if (b->nt)
+      KB_STEP(1, true);
+    else
+      KB_STEP(1, false);
+  }
+#undef KB_STEP
+  if (ev) (void)hipEventRecord(ev[2], st);
+  if (b->nplane) {
+    const dim3 gp((b->nplane + 255) / 256), bp(256);
+    if (par == 0)
+      hipLaunchKernelGGL((kb_outlet<Q, ST, 0>), gp, bp, 0, st, b->d_dom, b->ndom, b->nplane);
+    else
+      hipLaunchKernelGGL((kb_outlet<Q, ST, 1>), gp, bp, 0, st, b->d_dom, b->ndom, b->nplane);
+  }
+  if (ev) (void)hipEventRecord(ev[3], st);
+  return hipGetLastError();
+}
+
+hipError_t batch_launch(lbm_batch* b, int par, hipStream_t st, hipEvent_t* ev = nullptr) {
+  if (b->Q == 9) {
+    switch (b->ST) {
+      case 0: return batch_launch_t<9, 0>(b, par, st, ev);
+      case 1: return batch_launch_t<9, 1>(b, par, st, ev);
+      default: return batch_launch_t<9, 2>(b, par, st, ev);
+    }
+  }
+  switch (b->ST) {
+    case 0: return batch_launch_t<19, 0>(b, par, st, ev);
+    case 1: return batch_launch_t<19, 1>(b, par, st, ev);
+    default: return batch_launch_t<19, 2>(b, par, st, ev);
+  }
+}
+
+int batch_graph(lbm_batch* b) {
+  batch_drop_graph(b);
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t err = batch_launch(b, 0, b->cap);
+  if (err == hipSuccess) err = batch_launch(b, 1, b->cap);
+  hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return fail(LBM_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
+  }
+  hipError_t e3 = hipGraphInstantiate(&b->g_pair, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e3));
+  return LBM_OK;
+}
+
+void batch_sync_views(lbm_batch* b) {
+  for (auto* v : b->views) v->steps = b->steps;
+}
+
+int batch_time_steps(lbm_batch* b, int n, double* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, b->stream));
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = batch_launch(b, (int)(b->steps & 1), b->stream);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return fail(LBM_EDEVICE, hipGetErrorString(e));
+    }
+    b->steps += 1;
+  }
+  HIPCHK(hipEventRecord(e1, b->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = t / n;
+  return LBM_OK;
+}
+
+std::mutex g_btune_mu;
+std::map<std::string, TuneEntry> g_btune_cache;
+std::map<std::string, int> g_btune_bpc;
+
+std::string batch_key(const lbm_batch* b) {
+  std::string k = "q" + std::to_string(b->Q) + " st" + std::to_string(b->ST) + " n" + std::to_string(b->ndom);
+  for (auto* v : b->views)
+    k += " " + std::to_string(v->P.nx) + "x" + std::to_string(v->P.ny) + "x" + std::to_string(v->P.nz);
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_state_bytes(int ndom, const lbm_params* p, size_t* bytes) {
+  int rc = batch_validate(ndom, p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "null output");
+  std::vector<size_t> off;
+  *bytes = batch_layout(ndom, p, off);
+  return LBM_OK;
+}
+
+int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, const float* const* u0_dev,
+                   void* state_dev, size_t state_bytes, void* stream, lbm_batch** out) {
+  int rc = batch_validate(ndom, p);
+  if (rc) return rc;
+  if (!out || !phi0_dev || !state_dev) return fail(LBM_EINVAL, "null pointer argument");
+  if (((uintptr_t)state_dev) & 255) return fail(LBM_EINVAL, "state buffer must be 256-byte aligned");
+  lbm_batch* b = new lbm_batch();
+  const size_t total = batch_layout(ndom, p, b->off);
+  if (state_bytes < total) {
+    delete b;
+    return fail(LBM_ENOMEM, "state buffer smaller than lbm_batch_state_bytes()");
+  }
+  b->ndom = ndom;
+  b->Q = p[0].lattice;
+  b->ST = p[0].storage;
+  b->base = (char*)state_dev;
+  b->stream = (hipStream_t)stream;
+  b->views.assign(ndom, nullptr);
+  for (int d = 0; d < ndom && rc == LBM_OK; ++d) {
+    if (!phi0_dev[d]) {
+      rc = fail(LBM_EINVAL, "null phi0 for domain " + std::to_string(d));
+      break;
+    }
+    b->views[d] = new_sim(&p[d], b->base + b->off[d], b->stream, &rc);
+    if (rc == LBM_OK) rc = init_kernels(b->views[d], phi0_dev[d], u0_dev ? u0_dev[d] : nullptr);
+  }
+  if (rc == LBM_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(LBM_EDEVICE, "stream create");
+  if (rc == LBM_OK) rc = batch_tables(b);
+  if (rc) {
+    lbm_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int n) {
+  if (!b || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
+  if (n >= 2 && !b->g_pair) {
+    int rc = batch_graph(b);
+    if (rc) return rc;
+  }
+  while (n > 0) {
+    if ((b->steps & 1) || n == 1) {
+      HIPCHK(batch_launch(b, (int)(b->steps & 1), b->stream));
+      b->steps += 1;
+      n -= 1;
+    } else {
+      HIPCHK(hipGraphLaunch(b->g_pair, b->stream));
+      b->steps += 2;
+      n -= 2;
+    }
+  }
+  return LBM_OK;
+}
+
+long long lbm_batch_steps_done(const lbm_batch* b) { return b ? b->steps : -1; }
+
+int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic) {
+  if (!b || !mass || !kinetic) return fail(LBM_EINVAL, "null argument");
+  batch_sync_views(b);
+  int worst = LBM_OK;
+  for (int d = 0; d < b->ndom; ++d) {
+    int rc = lbm_reduce(b->views[d], &mass[d], &kinetic[d]);
+    if (rc == LBM_EUNSTABLE) worst = rc;
+    else if (rc) return rc;
+  }
+  if (worst) return fail(worst, "non-finite mass or kinetic energy in a domain");
+  return LBM_OK;
+}
+
+int lbm_batch_fields(lbm_batch* b, int dom, unsigned mask, float* phi_dev, float* u_dev, float* p_dev) {
+  if (!b || dom < 0 || dom >= b->ndom) return fail(LBM_EINVAL, "bad handle or domain");
+  batch_sync_views(b);
+  return lbm_fields(b->views[dom], mask, phi_dev, u_dev, p_dev);
+}
+
+int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, float* u_dev) {
+  if (!b || dom < 0 || dom >= b->ndom) return fail(LBM_EINVAL, "bad handle or domain");
+  batch_sync_views(b);
+  return lbm_export_state(b->views[dom], h_dev, g_dev, u_dev);
+}
+
+int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length) {
+  if (!b || !length) return fail(LBM_EINVAL, "null argument");
+  batch_sync_views(b);
+  int maxz = 0;
+  for (auto* v : b->views) maxz = std::max(maxz, v->Q == 9 ? v->P.ny : v->P.nz);
+  if (maxz > b->count_cap) {
+    if (b->d_count) hipFree(b->d_count);
+    b->d_count = nullptr;
+    HIPCHK(hipMalloc(&b->d_count, sizeof(int) * maxz));
+    b->count_cap = maxz;
+  }
+  std::vector<int> cnt(maxz);
+  for (int d = 0; d < b->ndom; ++d) {
+    lbm_sim* v = b->views[d];
+    HIPCHK(launch_phi(v));
+    const int planes = v->Q == 9 ? v->P.ny : v->P.nz;
+    hipLaunchKernelGGL(k_plane_count, dim3(planes), dim3(256), 0, b->stream, (const float*)v->out_buf(v->parity()),
+                       v->K.plane, planes, threshold, b->d_count);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cnt.data(), b->d_count, sizeof(int) * planes, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int L = planes;
+    for (int z = 0; z < planes; ++z)
+      if (cnt[z] == 0) {
+        L = z;
+        break;
+      }
+    length[d] = L;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal) {
+  if (!b) return fail(LBM_EINVAL, "null handle");
+  const int t = bx * by;
+  if (bx < 16 || bx % 16 || by < 1 || (t != 64 && t != 128 && t != 256 && t != 512) || blocks_per_cu < 1 ||
+      blocks_per_cu > 64)
+    return fail(LBM_EINVAL, "bad launch shape");
+  b->bx = bx;
+  b->by = by;
+  b->bpc = blocks_per_cu;
+  b->nt = nontemporal ? 1 : 0;
+  return batch_tables(b);
+}
+
+int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blocks_per_cu, int* nontemporal,
+                       double* ms_per_step) {
+  if (!b || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
+  const std::string key = batch_key(b);
+  TuneEntry best = {b->bx, b->by, b->nt, 1e30};
+  int best_bpc = b->bpc;
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    auto it = g_btune_cache.find(key);
+    if (it != g_btune_cache.end()) {
+      best = it->second;
+      best_bpc = g_btune_bpc[key];
+      cached = true;
+    }
+  }
+  if (!cached) {
+    static const int cand[][2] = {{32, 8}, {32, 4}, {64, 4}, {16, 16}, {32, 16}, {64, 2}, {16, 8}};
+    static const int bpcs[] = {2, 4, 8};
+    for (const auto& cb : cand)
+      for (int bp : bpcs)
+        for (int nt = 0; nt < 2; ++nt) {
+          int rc = lbm_batch_set_launch(b, cb[0], cb[1], bp, nt);
+          double ms = 0.0;
+          if (rc == LBM_OK) rc = batch_time_steps(b, 2, &ms);
+          if (rc == LBM_OK) rc = batch_time_steps(b, trial_steps, &ms);
+          if (rc) return rc;
+          if (ms < best.ms) {
+            best = {cb[0], cb[1], nt, ms};
+            best_bpc = bp;
+          }
+        }
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune_cache[key] = best;
+    g_btune_bpc[key] = best_bpc;
+  }
+  int rc = lbm_batch_set_launch(b, best.bx, best.by, best_bpc, best.nt);
+  if (rc) return rc;
+  if (bx) *bx = best.bx;
+  if (by) *by = best.by;
+  if (blocks_per_cu) *blocks_per_cu = best_bpc;
+  if (nontemporal) *nontemporal = best.nt;
+  if (ms_per_step) *ms_per_step = best.ms;
+  return LBM_OK;
+}
+
+int lbm_batch_kernel_times(lbm_batch* b, int n, double* out_ms) {
+  if (!b || n < 1 || !out_ms) return fail(LBM_EINVAL, "bad argument");
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  double acc[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = batch_launch(b, (int)(b->steps & 1), b->stream, ev);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, hipGetErrorString(e));
+    b->steps += 1;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      acc[k] += ms;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  for (int k = 0; k < 3; ++k) out_ms[k] = acc[k] / n;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  for (auto* v : b->views)
+    if (v) lbm_destroy(v);
+  if (b->d_dom) hipFree(b->d_dom);
+  if (b->d_tile_dom) hipFree(b->d_tile_dom);
+  if (b->d_count) hipFree(b->d_count);
+  if (b->cap) hipStreamDestroy(b->cap);
+  delete b;
 }
 
 }  // extern "C"

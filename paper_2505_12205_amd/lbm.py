@@ -68,6 +68,20 @@ def _load():
     L.lbm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.lbm_destroy.argtypes = [vp]
+    L.lbm_batch_state_bytes.argtypes = [C.c_int, P, C.POINTER(sz)]
+    L.lbm_batch_init.argtypes = [C.c_int, P, C.POINTER(vp), C.POINTER(vp), vp, sz, vp, C.POINTER(vp)]
+    L.lbm_batch_step.argtypes = [vp, C.c_int]
+    L.lbm_batch_steps_done.argtypes = [vp]
+    L.lbm_batch_steps_done.restype = C.c_longlong
+    L.lbm_batch_reduce.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbm_batch_fields.argtypes = [vp, C.c_int, C.c_uint, vp, vp, vp]
+    L.lbm_batch_export_state.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.lbm_batch_intact_length.argtypes = [vp, C.c_float, C.POINTER(C.c_int)]
+    L.lbm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.lbm_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lbm_batch_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
+    L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_version.restype = C.c_char_p
     return L
@@ -78,7 +92,10 @@ lib = _load()
 EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fields", "lbm_reduce",
             "lbm_export_state", "lbm_import_state", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
             "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_autotune",
-            "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version")
+            "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version",
+            "lbm_batch_state_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_steps_done",
+            "lbm_batch_reduce", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
+            "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_kernel_times", "lbm_batch_destroy")
 
 
 def _check(rc):
@@ -243,6 +260,116 @@ class Sim:
         """Mean ms of (phase-field pass, fused step kernel, boundary planes) over n eager steps."""
         out = (C.c_double * 3)()
         _check(lib.lbm_kernel_times(self._h, int(n), out))
+        return tuple(out)
+
+
+class Batch:
+    """Many independent domains (same lattice and storage) advanced together.
+
+    domains: list of (cfg, phi0, u0) as produced by workloads."""
+
+    def __init__(self, domains, storage: str = "fp32", device="cuda", stream=None):
+        self.storage = storage
+        self.device = torch.device(device)
+        self.cfgs = [dict(d[0]) for d in domains]
+        self.ndom = len(domains)
+        arr = (Params * self.ndom)()
+        for i, d in enumerate(domains):
+            arr[i] = make_params(d[0], storage)
+        self.params = arr
+        self.shapes = [(p.nz, p.ny, p.nx) for p in arr]
+        self.q = arr[0].lattice
+        n = C.c_size_t()
+        _check(lib.lbm_batch_state_bytes(self.ndom, arr, C.byref(n)))
+        self.state = torch.empty(n.value // 4 + 64, dtype=torch.float32, device=self.device)
+        off = (-self.state.data_ptr()) % 256
+        self._base = self.state.data_ptr() + off
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        keep = []
+        phis = (C.c_void_p * self.ndom)()
+        us = (C.c_void_p * self.ndom)()
+        for i, (cfg, phi0, u0) in enumerate(domains):
+            t = torch.as_tensor(phi0, dtype=torch.float32).reshape(-1).to(self.device).contiguous()
+            keep.append(t)
+            phis[i] = t.data_ptr()
+            if u0 is not None:
+                tu = torch.as_tensor(u0, dtype=torch.float32).reshape(-1).to(self.device).contiguous()
+                keep.append(tu)
+                us[i] = tu.data_ptr()
+            else:
+                us[i] = None
+        h = C.c_void_p()
+        _check(lib.lbm_batch_init(self.ndom, arr, phis, us, self._base, n.value, self.stream.cuda_stream,
+                                  C.byref(h)))
+        self._h = h
+        self.stream.synchronize()
+        del keep
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and lib is not None:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            lib.lbm_batch_destroy(h)
+            self._h = None
+
+    @property
+    def nodes(self) -> int:
+        return sum(int(s[0]) * int(s[1]) * int(s[2]) for s in self.shapes)
+
+    def step(self, n: int = 1):
+        _check(lib.lbm_batch_step(self._h, int(n)))
+        return self
+
+    @property
+    def steps_done(self) -> int:
+        return int(lib.lbm_batch_steps_done(self._h))
+
+    def reduce(self):
+        m = (C.c_double * self.ndom)()
+        k = (C.c_double * self.ndom)()
+        _check(lib.lbm_batch_reduce(self._h, m, k))
+        return list(m), list(k)
+
+    def fields(self, dom: int):
+        sh = self.shapes[dom]
+        phi = torch.empty(sh, dtype=torch.float32, device=self.device)
+        u = torch.empty((3,) + sh, dtype=torch.float32, device=self.device)
+        p = torch.empty(sh, dtype=torch.float32, device=self.device)
+        _check(lib.lbm_batch_fields(self._h, dom, FIELD_PHI | FIELD_U | FIELD_P, phi.data_ptr(), u.data_ptr(),
+                                    p.data_ptr()))
+        self.stream.synchronize()
+        return phi, u, p
+
+    def export_state(self, dom: int):
+        sh = self.shapes[dom]
+        h = torch.empty((self.q,) + sh, dtype=torch.float32, device=self.device)
+        g = torch.empty((self.q,) + sh, dtype=torch.float32, device=self.device)
+        u = torch.empty((3,) + sh, dtype=torch.float32, device=self.device)
+        _check(lib.lbm_batch_export_state(self._h, dom, h.data_ptr(), g.data_ptr(), u.data_ptr()))
+        self.stream.synchronize()
+        return h, g, u
+
+    def intact_length(self, threshold: float = 0.5):
+        out = (C.c_int * self.ndom)()
+        _check(lib.lbm_batch_intact_length(self._h, float(threshold), out))
+        return list(out)
+
+    def set_launch(self, bx: int, by: int, blocks_per_cu: int = 4, nontemporal: bool = False):
+        _check(lib.lbm_batch_set_launch(self._h, bx, by, blocks_per_cu, 1 if nontemporal else 0))
+        return self
+
+    def autotune(self, trial_steps: int = 4):
+        bx, by, bpc, nt, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        _check(lib.lbm_batch_autotune(self._h, int(trial_steps), C.byref(bx), C.byref(by), C.byref(bpc),
+                                      C.byref(nt), C.byref(ms)))
+        return bx.value, by.value, bpc.value, bool(nt.value), ms.value
+
+    def kernel_times(self, n: int):
+        out = (C.c_double * 3)()
+        _check(lib.lbm_batch_kernel_times(self._h, int(n), out))
         return tuple(out)
 
 
