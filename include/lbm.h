@@ -153,8 +153,13 @@ int lbm_get_tile(const lbm_sim* s, int* bx, int* by);
 /* Non-temporal hint (nonzero) on the population stores of the fused kernel. */
 int lbm_set_store_hint(lbm_sim* s, int nontemporal);
 
-/* Autotuner: times trial_steps eager steps for each candidate tile shape and
- * store hint and keeps the fastest; results are cached per (lattice, storage,
+/* Resident blocks per compute unit of the persistent launches (1..64): the
+ * interior kernels run as about CUs x blocks_per_cu blocks, each walking a
+ * contiguous chunk of tiles. */
+int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu);
+
+/* Autotuner: times trial_steps eager steps for each candidate tile shape,
+ * blocks per compute unit and store hint and keeps the fastest; results are cached per (lattice, storage,
  * grid, boundary set) for the life of the process, so later simulations of
  * the same shape take the cached choice without trials.  The state advances
  * by the trial steps.  Synchronises.  Outputs (nullable): chosen bx, by,

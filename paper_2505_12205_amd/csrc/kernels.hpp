@@ -1,10 +1,12 @@
 // kernels.hpp -- gfx950 device code of the phase-field LBM step.
 //
-// One step at parity P (P = steps % 2) is
-//   k_phi<P>   : phi(x) = sum_a h_a(x)                      (Eq. phase_field_variable)
-//   k_step<P>  : stencil of phi, macroscopic update, both collisions and the
-//                in-place AA streaming of both population sets
-//   k_outlet<P>: convective outflow plane (only with an outlet face)
+// One step at parity P (P = steps % 2) is, over a table of domains,
+//   kb_interior<P, PHI>, kb_faces<P, PHI>: phi(x) = sum_a h_a(x) (Eq. phase_field_variable)
+//   kb_interior<P, STEP>, kb_faces<P, STEP>: stencil of phi, macroscopic update,
+//       both collisions and the in-place AA streaming of both population sets
+//   kb_outlet<P>: convective outflow plane (only with an outlet face)
+// Interior nodes (away from the faces of non-periodic axes) take the fast
+// path with precomputed neighbour offsets; face-layer nodes the general path.
 //
 // Storage is structure-of-arrays, pop[a][node] with node = x + nx*(y + ny*z)
 // (x fastest), one array per set; streaming is the AA pattern:
@@ -476,11 +478,6 @@ __device__ __forceinline__ void kahan_sum(const float* v, float& hi, float& lo) 
 }
 
 // ---------------------------------------------------------------------------
-// k_phi: phase field of the current state (defined after the neighbour
-// helpers below)
-// ---------------------------------------------------------------------------
-
-// ---------------------------------------------------------------------------
 // node physics (shared by the fast interior path and the general path)
 // ---------------------------------------------------------------------------
 struct Stress {  // second moments sum g e e
@@ -914,13 +911,6 @@ __device__ __forceinline__ bool box_coords(const Box& X, const Tiling& T, int c[
   return tile_node(X, T, xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x, c);
 }
 
-template <int Q, int ST, int ODD, bool NT>
-__global__ __launch_bounds__(512) void k_step(KParams P, KBufs B, Tiling T, Box X) {
-  int c[3];
-  if (!box_coords(X, T, c)) return;
-  step_fast<Q, ST, ODD, NT>(P, B, c);
-}
-
 // Face layers of non-periodic axes, enumerated slab by slab without overlap:
 // axis 0 faces (whole y-z planes), then axis 1 faces inside the x range left,
 // then axis 2 faces inside the x-y range left.
@@ -952,18 +942,9 @@ __device__ __forceinline__ void face_coords(const KParams& P, const Faces& F, in
   c[1] = F.y0 + r / F.nxi;
 }
 
-template <int Q, int ST, int ODD, bool NT>
-__global__ __launch_bounds__(256) void k_step_faces(KParams P, KBufs B, Faces F) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= F.n0 + F.n1 + F.n2) return;
-  int c[3];
-  face_coords(P, F, t, c);
-  step_general<Q, ST, ODD, NT>(P, B, c);
-}
-
 // ---------------------------------------------------------------------------
-// k_phi: phase field phi = sum_a h_a of the current state (Eq.
-// phase_field_variable), compensated sum; interior box and face layers
+// phase field phi = sum_a h_a of the current state (Eq. phase_field_variable),
+// compensated sum; interior nodes and face-layer nodes
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int ODD>
 __device__ __forceinline__ void phi_fast(const KParams& P, const KBufs& B, const int c[3]) {
@@ -1002,22 +983,6 @@ __device__ __forceinline__ void phi_general(const KParams& P, const KBufs& B, co
   B.phi_out[node] = phi;
 }
 
-template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(512) void k_phi(KParams P, KBufs B, Tiling T, Box X) {
-  int c[3];
-  if (!box_coords(X, T, c)) return;
-  phi_fast<Q, ST, ODD>(P, B, c);
-}
-
-template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(256) void k_phi_faces(KParams P, KBufs B, Faces F) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= F.n0 + F.n1 + F.n2) return;
-  int c[3];
-  face_coords(P, F, t, c);
-  phi_general<Q, ST, ODD>(P, B, c);
-}
-
 // ---------------------------------------------------------------------------
 // k_outlet: convective outflow (appendix B) after the step of parity ODD
 // ---------------------------------------------------------------------------
@@ -1049,15 +1014,9 @@ __device__ __forceinline__ void outlet_node(const KParams& P, const KBufs& B, in
   }
 }
 
-template <int Q, int ST, int ODD>
-__global__ __launch_bounds__(256) void k_outlet(KParams P, KBufs B) {
-  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pi >= P.plane) return;
-  outlet_node<Q, ST, ODD>(P, B, pi);
-}
-
 // ---------------------------------------------------------------------------
-// batched form: many domains (own parameters, own buffers) per launch
+// Launches over a table of domains (one domain for a single simulation, many
+// for the batched form): every domain has its own parameters and buffers.
 // ---------------------------------------------------------------------------
 struct DomDev {
   KParams K;
@@ -1079,7 +1038,7 @@ __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D,
   const int t0 = L * chunk;
   const int t1 = min(t0 + chunk, ntiles);
   for (int t = t0; t < t1; ++t) {
-    const int d = tile_dom[t];
+    const int d = tile_dom ? tile_dom[t] : 0;
     const DomDev& dm = D[d];
     Tiling T;
     T.bx = bx;

@@ -1,5 +1,9 @@
 // lbm.hip -- host runtime and C ABI (include/lbm.h) of the gfx950
 // phase-field lattice Boltzmann library.
+//
+// A simulation and a batch step through the same kernels: the launches run
+// over a device table of domains (one entry for a simulation, many for a
+// batch), so a domain advances bit for bit the same way in both.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,19 +43,12 @@ struct Layout {
 };
 
 int pop_size(int storage) { return storage == LBM_FP32 ? 4 : 2; }
-
 int axis_of(int lattice) { return lattice == LBM_D2Q9 ? 1 : 2; }
-
 int plane_of(const lbm_params& p) { return p.lattice == LBM_D2Q9 ? p.nx : p.nx * p.ny; }
 
-bool has_outlet(const lbm_params& p) {
+bool has_bc(const lbm_params& p, int bc) {
   for (int f = 0; f < 6; ++f)
-    if (p.bc[f] == LBM_BC_CONVECTIVE_OUTLET) return true;
-  return false;
-}
-bool has_inlet(const lbm_params& p) {
-  for (int f = 0; f < 6; ++f)
-    if (p.bc[f] == LBM_BC_VELOCITY_INLET) return true;
+    if (p.bc[f] == bc) return true;
   return false;
 }
 
@@ -62,8 +59,7 @@ int validate(const lbm_params* p) {
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz = 1");
   if (p->lattice == LBM_D3Q19 && p->nz < 2) return fail(LBM_EINVAL, "D3Q19 needs nz >= 2");
   const double nodes = (double)p->nx * p->ny * p->nz;
-  if (nodes * 19 >= 2147483647.0 * 4) return fail(LBM_EINVAL, "grid too large for one domain");
-  if (nodes >= 2147483647.0) return fail(LBM_EINVAL, "grid too large for one domain");
+  if (nodes >= 2147483647.0 / 4) return fail(LBM_EINVAL, "grid too large for one domain");
   if (!(p->tau_h > -0.5) || !(p->tau_l > -0.5)) return fail(LBM_EINVAL, "tau must exceed -1/2");
   if (!(p->xi > 0.0)) return fail(LBM_EINVAL, "xi must be positive");
   if (!(p->rho_l > 0.0) || !(p->rho_h > 0.0)) return fail(LBM_EINVAL, "densities must be positive");
@@ -81,14 +77,13 @@ int validate(const lbm_params* p) {
         return fail(LBM_EINVAL, "faces of the z axis must be periodic in 2D");
       continue;
     }
-    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC))
-      return fail(LBM_EINVAL, "periodic faces must be paired");
+    if ((lo == LBM_BC_PERIODIC) != (hi == LBM_BC_PERIODIC)) return fail(LBM_EINVAL, "periodic faces must be paired");
     if (lo == LBM_BC_CONVECTIVE_OUTLET || hi == LBM_BC_VELOCITY_INLET)
       return fail(LBM_EUNSUPPORTED, "inlet only on the minus face, outlet only on the plus face");
     if ((lo == LBM_BC_VELOCITY_INLET || hi == LBM_BC_CONVECTIVE_OUTLET) && d != ax)
       return fail(LBM_EUNSUPPORTED, "inlet/outlet only on the last axis (z in 3D, y in 2D)");
   }
-  if (has_outlet(*p)) {
+  if (has_bc(*p, LBM_BC_CONVECTIVE_OUTLET)) {
     const int n = ax == 2 ? p->nz : p->ny;
     if (n < 3) return fail(LBM_EINVAL, "outlet axis needs at least 3 nodes");
     if (p->outlet_mode != LBM_OUTLET_LOCAL)
@@ -114,7 +109,7 @@ Layout layout_of(const lbm_params& p) {
   L.phi1 = off;
   if (p.storage != LBM_FP32) off = align256(off + N * 4);
   L.obuf = off;
-  if (has_outlet(p)) off = align256(off + 2 * Q * (size_t)plane_of(p) * 4);
+  if (has_bc(p, LBM_BC_CONVECTIVE_OUTLET)) off = align256(off + 2 * Q * (size_t)plane_of(p) * 4);
   L.total = off;
   return L;
 }
@@ -147,18 +142,18 @@ KParams kparams_of(const lbm_params& p) {
   K.in_u = (float)p.inlet_u;
   K.two_over_xi = (float)(2.0 / p.xi);
   K.clamp = (p.variant_flags & LBM_VF_CLAMP_PHI) ? 1 : 0;
-  K.has_inlet = has_inlet(p) ? 1 : 0;
-  K.has_outlet = has_outlet(p) ? 1 : 0;
+  K.has_inlet = has_bc(p, LBM_BC_VELOCITY_INLET) ? 1 : 0;
+  K.has_outlet = has_bc(p, LBM_BC_CONVECTIVE_OUTLET) ? 1 : 0;
   return K;
 }
 
-Tiling tiling_of(const lbm_params& p, int bx, int by) {
+Tiling tiling_of(int nx, int ny, int nz, int bx, int by) {
   Tiling T;
   T.bx = bx;
   T.by = by;
-  T.ntx = (p.nx + bx - 1) / bx;
-  T.nty = (p.ny + by - 1) / by;
-  T.ntiles = T.ntx * T.nty * p.nz;
+  T.ntx = (nx + bx - 1) / bx;
+  T.nty = (ny + by - 1) / by;
+  T.ntiles = (nx > 0 && ny > 0) ? T.ntx * T.nty * nz : 0;
   return T;
 }
 
@@ -167,7 +162,7 @@ bool axis_periodic(const lbm_params& p, int d) {
   return d >= ndim || p.bc[2 * d] == LBM_BC_PERIODIC;
 }
 
-// interior box of the fused kernel and the face slabs around it
+// interior box (fast path) and the face slabs around it (general path)
 void split_domain(const lbm_params& p, Box& X, Faces& F) {
   const int n[3] = {p.nx, p.ny, p.nz};
   int o[3], e[3];
@@ -191,27 +186,35 @@ void split_domain(const lbm_params& p, Box& X, Faces& F) {
   F.n2 = axis_periodic(p, 2) ? 0 : 2 * e[0] * e[1];
 }
 
-Tiling box_tiling(const Box& X, int bx, int by) {
-  Tiling T;
-  T.bx = bx;
-  T.by = by;
-  T.ntx = (X.nx + bx - 1) / bx;
-  T.nty = (X.ny + by - 1) / by;
-  T.ntiles = (X.nx > 0 && X.ny > 0) ? T.ntx * T.nty * X.nz : 0;
-  return T;
-}
-
 void default_tile(const lbm_params& p, int& bx, int& by) {
   if (p.nx >= 64 && p.nx % 64 == 0) {
     bx = 64;
     by = 4;
-  } else if (p.nx % 32 == 0) {
+  } else {
     bx = 32;
     by = 8;
-  } else {
-    bx = 64;
-    by = 4;
   }
+}
+
+bool tile_ok(int bx, int by) {
+  const int t = bx * by;
+  return bx >= 16 && bx % 16 == 0 && by >= 1 && (t == 64 || t == 128 || t == 256 || t == 512);
+}
+
+// device table and launch geometry of a set of domains
+struct LaunchSet {
+  DomDev* d_dom = nullptr;
+  int* d_tile = nullptr;  // tile -> domain (null for a single domain)
+  int ndom = 0, ntiles = 0, nface = 0, nplane = 0;
+  int bx = 64, by = 4, bpc = 4, nt = 0;
+  int grid = 1, chunk = 1;
+};
+
+void free_launch(LaunchSet& ls) {
+  if (ls.d_dom) (void)hipFree(ls.d_dom);
+  if (ls.d_tile) (void)hipFree(ls.d_tile);
+  ls.d_dom = nullptr;
+  ls.d_tile = nullptr;
 }
 
 }  // namespace
@@ -219,8 +222,7 @@ void default_tile(const lbm_params& p, int& bx, int& by) {
 struct lbm_sim {
   lbm_params P;
   KParams K;
-  Tiling T;             // whole domain (phi pass and auxiliary kernels)
-  Tiling TB;            // interior box of the fused kernel
+  Tiling T;  // whole-domain tiling of the auxiliary kernels
   Box box;
   Faces faces;
   Layout L;
@@ -234,15 +236,14 @@ struct lbm_sim {
   double* res;          // 2 doubles on the device
   double* res_host;     // pinned
   int nparts;
+  LaunchSet ls;
   hipGraphExec_t g_pair, g_many;
   int many_pairs;
-  bool graphs_ok;
-  bool nt;              // non-temporal population stores in the fused kernel
   float* phi(int i) { return (float*)(base + (i == 0 ? L.phi0 : L.phi1)); }
   void* h() { return base + L.h; }
   void* g() { return base + L.g; }
   float* u() { return (float*)(base + L.u); }
-  float* obuf() { return has_outlet(P) ? (float*)(base + L.obuf) : nullptr; }
+  float* obuf() { return K.has_outlet ? (float*)(base + L.obuf) : nullptr; }
   int parity() const { return (int)(steps & 1); }
   // 16-bit forms ping-pong two phase-field buffers: at parity p the stored
   // populations were encoded with phi[p] and this step's phi goes to phi[1-p].
@@ -263,113 +264,150 @@ struct lbm_sim {
 
 namespace {
 
-// ---- template dispatch ----------------------------------------------------
-template <int Q, int ST>
-void launch_phi_kernels(lbm_sim* s, int par, hipStream_t st) {
-  KBufs B = s->bufs(par);
-  const Tiling& TB = s->TB;
-  const dim3 block(TB.bx * TB.by);
-  if (TB.ntiles > 0) {
-    if (par == 0)
-      hipLaunchKernelGGL((k_phi<Q, ST, 0>), dim3(TB.ntiles), block, 0, st, s->K, B, TB, s->box);
-    else
-      hipLaunchKernelGGL((k_phi<Q, ST, 1>), dim3(TB.ntiles), block, 0, st, s->K, B, TB, s->box);
+// Fill the device table of the domains `v[0..n)` with launch shape (bx, by,
+// blocks per CU, store hint); allocates the table (replacing any old one).
+int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bpc, int nt) {
+  std::vector<DomDev> dom(n);
+  std::vector<int> tile_dom;
+  int tb = 0, fb = 0, pb = 0;
+  for (int d = 0; d < n; ++d) {
+    lbm_sim* s = v[d];
+    DomDev& m = dom[d];
+    memset(&m, 0, sizeof m);
+    m.K = s->K;
+    for (int par = 0; par < 2; ++par) {
+      m.B[par] = s->bufs(par);
+      m.Bo[par] = s->bufs(par);
+      m.Bo[par].ref = s->out_buf(par);  // the outlet decodes what this step wrote
+    }
+    m.X = s->box;
+    m.F = s->faces;
+    const Tiling TB = tiling_of(s->box.nx, s->box.ny, s->box.nz, bx, by);
+    m.ntx = TB.ntx;
+    m.nty = TB.nty;
+    m.ntiles = TB.ntiles;
+    m.tile_base = tb;
+    m.face_base = fb;
+    m.plane_base = pb;
+    if (n > 1) tile_dom.insert(tile_dom.end(), (size_t)TB.ntiles, d);
+    tb += TB.ntiles;
+    fb += s->faces.n0 + s->faces.n1 + s->faces.n2;
+    pb += s->K.has_outlet ? s->K.plane : 0;
   }
-  const int nface = s->faces.n0 + s->faces.n1 + s->faces.n2;
-  if (nface > 0) {
-    const dim3 gf((nface + 255) / 256), bf(256);
-    if (par == 0)
-      hipLaunchKernelGGL((k_phi_faces<Q, ST, 0>), gf, bf, 0, st, s->K, B, s->faces);
-    else
-      hipLaunchKernelGGL((k_phi_faces<Q, ST, 1>), gf, bf, 0, st, s->K, B, s->faces);
+  free_launch(ls);
+  ls.ndom = n;
+  ls.ntiles = tb;
+  ls.nface = fb;
+  ls.nplane = pb;
+  ls.bx = bx;
+  ls.by = by;
+  ls.bpc = bpc;
+  ls.nt = nt;
+  HIPCHK(hipMalloc(&ls.d_dom, sizeof(DomDev) * n));
+  HIPCHK(hipMemcpy(ls.d_dom, dom.data(), sizeof(DomDev) * n, hipMemcpyHostToDevice));
+  if (n > 1 && tb) {
+    HIPCHK(hipMalloc(&ls.d_tile, sizeof(int) * tb));
+    HIPCHK(hipMemcpy(ls.d_tile, tile_dom.data(), sizeof(int) * tb, hipMemcpyHostToDevice));
   }
+  int dev = 0, cus = 256;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // persistent launch: about bpc resident blocks per compute unit, each
+  // walking a contiguous chunk of tiles
+  const int want = std::max(1, std::min(std::max(tb, 1), cus * bpc));
+  ls.chunk = std::max(1, (tb + want - 1) / want);
+  ls.grid = std::max(1, (tb + ls.chunk - 1) / ls.chunk);
+  return LBM_OK;
 }
 
+template <int Q, int ST, int PAR>
+void launch_phi_set(const LaunchSet& ls, hipStream_t st) {
+  const dim3 gi(ls.grid), bi(ls.bx * ls.by);
+  if (ls.ntiles)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile, ls.ntiles,
+                       ls.chunk, ls.bx, ls.by);
+  if (ls.nface)
+    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, false, true>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
+                       ls.d_dom, ls.ndom, ls.nface);
+}
+
+template <int Q, int ST, int PAR, bool NT>
+void launch_collide_set(const LaunchSet& ls, hipStream_t st) {
+  const dim3 gi(ls.grid), bi(ls.bx * ls.by);
+  if (ls.ntiles)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile, ls.ntiles,
+                       ls.chunk, ls.bx, ls.by);
+  if (ls.nface)
+    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NT, false>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
+                       ls.d_dom, ls.ndom, ls.nface);
+}
+
+// one step of parity `par`: phase-field pass, fused step, outlet planes;
+// events (nullable) bracket the three phases
 template <int Q, int ST>
-hipError_t launch_step_t(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
-  const KParams& K = s->K;
-  const Tiling& T = s->T;
-  const dim3 grid(T.ntiles), block(T.bx * T.by);
-  KBufs B = s->bufs(par);
+hipError_t launch_step_t(const LaunchSet& ls, int par, hipStream_t st, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], st);
-  launch_phi_kernels<Q, ST>(s, par, st);
+  if (par == 0)
+    launch_phi_set<Q, ST, 0>(ls, st);
+  else
+    launch_phi_set<Q, ST, 1>(ls, st);
   if (ev) (void)hipEventRecord(ev[1], st);
-  const Tiling& TB = s->TB;
-  if (TB.ntiles > 0) {
-    const dim3 gb(TB.ntiles);
-    if (s->nt) {
-      if (par == 0)
-        hipLaunchKernelGGL((k_step<Q, ST, 0, true>), gb, block, 0, st, K, B, TB, s->box);
-      else
-        hipLaunchKernelGGL((k_step<Q, ST, 1, true>), gb, block, 0, st, K, B, TB, s->box);
-    } else {
-      if (par == 0)
-        hipLaunchKernelGGL((k_step<Q, ST, 0, false>), gb, block, 0, st, K, B, TB, s->box);
-      else
-        hipLaunchKernelGGL((k_step<Q, ST, 1, false>), gb, block, 0, st, K, B, TB, s->box);
-    }
-  }
-  const int nface = s->faces.n0 + s->faces.n1 + s->faces.n2;
-  if (nface > 0) {
-    const dim3 gf((nface + 255) / 256), bf(256);
-    if (s->nt) {
-      if (par == 0)
-        hipLaunchKernelGGL((k_step_faces<Q, ST, 0, true>), gf, bf, 0, st, K, B, s->faces);
-      else
-        hipLaunchKernelGGL((k_step_faces<Q, ST, 1, true>), gf, bf, 0, st, K, B, s->faces);
-    } else {
-      if (par == 0)
-        hipLaunchKernelGGL((k_step_faces<Q, ST, 0, false>), gf, bf, 0, st, K, B, s->faces);
-      else
-        hipLaunchKernelGGL((k_step_faces<Q, ST, 1, false>), gf, bf, 0, st, K, B, s->faces);
-    }
+  if (par == 0) {
+    if (ls.nt)
+      launch_collide_set<Q, ST, 0, true>(ls, st);
+    else
+      launch_collide_set<Q, ST, 0, false>(ls, st);
+  } else {
+    if (ls.nt)
+      launch_collide_set<Q, ST, 1, true>(ls, st);
+    else
+      launch_collide_set<Q, ST, 1, false>(ls, st);
   }
   if (ev) (void)hipEventRecord(ev[2], st);
-  if (K.has_outlet) {
-    KBufs Bo = B;
-    Bo.ref = s->out_buf(par);
-    const dim3 pg((K.plane + 255) / 256), pb(256);
+  if (ls.nplane) {
+    const dim3 gp((ls.nplane + 255) / 256), bp(256);
     if (par == 0)
-      hipLaunchKernelGGL((k_outlet<Q, ST, 0>), pg, pb, 0, st, K, Bo);
+      hipLaunchKernelGGL((kb_outlet<Q, ST, 0>), gp, bp, 0, st, ls.d_dom, ls.ndom, ls.nplane);
     else
-      hipLaunchKernelGGL((k_outlet<Q, ST, 1>), pg, pb, 0, st, K, Bo);
+      hipLaunchKernelGGL((kb_outlet<Q, ST, 1>), gp, bp, 0, st, ls.d_dom, ls.ndom, ls.nplane);
   }
   if (ev) (void)hipEventRecord(ev[3], st);
   return hipGetLastError();
 }
 
-template <int Q>
-hipError_t launch_step_q(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev) {
-  switch (s->ST) {
-    case LBM_FP32: return launch_step_t<Q, 0>(s, par, st, ev);
-    case LBM_FP16_DEV: return launch_step_t<Q, 1>(s, par, st, ev);
-    default: return launch_step_t<Q, 2>(s, par, st, ev);
+hipError_t launch_step(const LaunchSet& ls, int Q, int ST, int par, hipStream_t st, hipEvent_t* ev = nullptr) {
+  if (Q == 9) {
+    if (ST == 0) return launch_step_t<9, 0>(ls, par, st, ev);
+    if (ST == 1) return launch_step_t<9, 1>(ls, par, st, ev);
+    return launch_step_t<9, 2>(ls, par, st, ev);
   }
-}
-
-hipError_t launch_step(lbm_sim* s, int par, hipStream_t st, hipEvent_t* ev = nullptr) {
-  return s->Q == 9 ? launch_step_q<9>(s, par, st, ev) : launch_step_q<19>(s, par, st, ev);
+  if (ST == 0) return launch_step_t<19, 0>(ls, par, st, ev);
+  if (ST == 1) return launch_step_t<19, 1>(ls, par, st, ev);
+  return launch_step_t<19, 2>(ls, par, st, ev);
 }
 
 template <int Q, int ST>
-hipError_t launch_phi_t(lbm_sim* s, hipStream_t st) {
-  launch_phi_kernels<Q, ST>(s, s->parity(), st);
+hipError_t launch_phi_t(const LaunchSet& ls, int par, hipStream_t st) {
+  if (par == 0)
+    launch_phi_set<Q, ST, 0>(ls, st);
+  else
+    launch_phi_set<Q, ST, 1>(ls, st);
   return hipGetLastError();
 }
 
-template <int Q>
-hipError_t launch_phi_q(lbm_sim* s, hipStream_t st) {
-  switch (s->ST) {
-    case LBM_FP32: return launch_phi_t<Q, 0>(s, st);
-    case LBM_FP16_DEV: return launch_phi_t<Q, 1>(s, st);
-    default: return launch_phi_t<Q, 2>(s, st);
-  }
-}
-
 hipError_t launch_phi(lbm_sim* s) {
-  return s->Q == 9 ? launch_phi_q<9>(s, s->stream) : launch_phi_q<19>(s, s->stream);
+  const int par = s->parity();
+  if (s->Q == 9) {
+    if (s->ST == 0) return launch_phi_t<9, 0>(s->ls, par, s->stream);
+    if (s->ST == 1) return launch_phi_t<9, 1>(s->ls, par, s->stream);
+    return launch_phi_t<9, 2>(s->ls, par, s->stream);
+  }
+  if (s->ST == 0) return launch_phi_t<19, 0>(s->ls, par, s->stream);
+  if (s->ST == 1) return launch_phi_t<19, 1>(s->ls, par, s->stream);
+  return launch_phi_t<19, 2>(s->ls, par, s->stream);
 }
 
+// ---- auxiliary kernels of one domain ----------------------------------------
 template <int Q, int ST>
 hipError_t launch_init_t(lbm_sim* s, const float* phi0, const float* u0) {
   const dim3 grid(s->T.ntiles), block(s->T.bx * s->T.by);
@@ -419,65 +457,51 @@ hipError_t launch_pressure_t(lbm_sim* s, float* po) {
                   : (s)->ST == 1 ? fn<19, 1>((s), __VA_ARGS__)                         \
                                  : fn<19, 2>((s), __VA_ARGS__)))
 
-void drop_graphs(lbm_sim* s) {
-  if (s->g_pair) hipGraphExecDestroy(s->g_pair);
-  if (s->g_many) hipGraphExecDestroy(s->g_many);
-  s->g_pair = s->g_many = nullptr;
-  s->graphs_ok = false;
+// ---- graphs ------------------------------------------------------------------
+void drop_graph(hipGraphExec_t& g) {
+  if (g) (void)hipGraphExecDestroy(g);
+  g = nullptr;
 }
 
-int capture(lbm_sim* s, int pairs, hipGraphExec_t* out) {
+int capture_pairs(const LaunchSet& ls, int Q, int ST, hipStream_t cap, int pairs, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   for (int i = 0; i < pairs && err == hipSuccess; ++i) {
-    err = launch_step(s, 0, s->cap);
-    if (err == hipSuccess) err = launch_step(s, 1, s->cap);
+    err = launch_step(ls, Q, ST, 0, cap);
+    if (err == hipSuccess) err = launch_step(ls, Q, ST, 1, cap);
   }
-  hipError_t e2 = hipStreamEndCapture(s->cap, &graph);
-  if (err != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
-    return fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(err));
+  hipError_t e2 = hipStreamEndCapture(cap, &graph);
+  if (err != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
   }
-  if (e2 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
   hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e3));
   return LBM_OK;
 }
 
+void drop_graphs(lbm_sim* s) {
+  drop_graph(s->g_pair);
+  drop_graph(s->g_many);
+}
+
 int build_graphs(lbm_sim* s) {
   drop_graphs(s);
-  // about 4M node updates per pair of steps or more per graph launch
+  // about 4M node updates or more per graph launch
   s->many_pairs = (int)std::max<size_t>(1, std::min<size_t>(64, (size_t)4000000 / std::max<size_t>(1, s->N)));
-  int rc = capture(s, 1, &s->g_pair);
+  int rc = capture_pairs(s->ls, s->Q, s->ST, s->cap, 1, &s->g_pair);
   if (rc) return rc;
-  if (s->many_pairs > 1) {
-    rc = capture(s, s->many_pairs, &s->g_many);
-    if (rc) return rc;
-  }
-  s->graphs_ok = true;
-  return LBM_OK;
+  if (s->many_pairs > 1) rc = capture_pairs(s->ls, s->Q, s->ST, s->cap, s->many_pairs, &s->g_many);
+  return rc;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* lbm_last_error(void) { return g_err.c_str(); }
-const char* lbm_version(void) { return "lbm-pf-gfx950 0.1"; }
-
-int lbm_state_bytes(const lbm_params* p, size_t* bytes) {
-  int rc = validate(p);
-  if (rc) return rc;
-  if (!bytes) return fail(LBM_EINVAL, "null output");
-  *bytes = layout_of(*p).total;
-  return LBM_OK;
+int set_launch(lbm_sim* s, int bx, int by, int bpc, int nt) {
+  drop_graphs(s);
+  lbm_sim* v[1] = {s};
+  return build_launch(s->ls, v, 1, bx, by, bpc, nt);
 }
-
-}  // extern "C"
-
-namespace {
 
 // simulation object on an existing state buffer; no launch
 lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
@@ -492,15 +516,13 @@ lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
   s->stream = stream;
   s->steps = 0;
   s->g_pair = s->g_many = nullptr;
-  s->graphs_ok = false;
-  s->nt = false;
+  s->many_pairs = 1;
   s->part = s->res = s->res_host = nullptr;
   s->cap = nullptr;
   int bx, by;
   default_tile(*p, bx, by);
   split_domain(*p, s->box, s->faces);
-  s->T = tiling_of(*p, bx, by);
-  s->TB = box_tiling(s->box, bx, by);
+  s->T = tiling_of(p->nx, p->ny, p->nz, bx, by);
   s->nparts = 1024;
   hipError_t e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&s->part, sizeof(double) * 2 * s->nparts);
@@ -511,7 +533,11 @@ lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
     lbm_destroy(s);
     return nullptr;
   }
-  *rc = LBM_OK;
+  *rc = set_launch(s, bx, by, 4, 0);
+  if (*rc) {
+    lbm_destroy(s);
+    return nullptr;
+  }
   return s;
 }
 
@@ -527,9 +553,80 @@ int init_kernels(lbm_sim* s, const float* phi0_dev, const float* u0_dev) {
   return LBM_OK;
 }
 
+// mean ms per eager step over n steps (events around the whole step)
+int time_steps(const LaunchSet& ls, int Q, int ST, hipStream_t st, long long& steps, int n, double* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = hipEventRecord(e0, st);
+  for (int i = 0; i < n && err == hipSuccess; ++i) {
+    err = launch_step(ls, Q, ST, (int)(steps & 1), st);
+    steps += 1;
+  }
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(LBM_EDEVICE, hipGetErrorString(err));
+  *ms = t / n;
+  return LBM_OK;
+}
+
+// per-phase mean ms over n eager steps
+int phase_times(const LaunchSet& ls, int Q, int ST, hipStream_t st, long long& steps, int n, double* out) {
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  double acc[3] = {0, 0, 0};
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < n && err == hipSuccess; ++i) {
+    err = launch_step(ls, Q, ST, (int)(steps & 1), st, ev);
+    steps += 1;
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(LBM_EDEVICE, hipGetErrorString(err));
+  for (int k = 0; k < 3; ++k) out[k] = acc[k] / n;
+  return LBM_OK;
+}
+
+struct TuneEntry {
+  int bx, by, bpc, nt;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune_cache;
+
+const int kTiles[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4}, {32, 4}, {16, 16}};
+const int kBpc[] = {2, 4, 8};
+
+std::string params_key(const lbm_params& p) {
+  char buf[200];
+  snprintf(buf, sizeof buf, "q%d st%d %dx%dx%d bc%d%d%d%d%d%d", p.lattice, p.storage, p.nx, p.ny, p.nz, p.bc[0],
+           p.bc[1], p.bc[2], p.bc[3], p.bc[4], p.bc[5]);
+  return buf;
+}
+
 }  // namespace
 
 extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_version(void) { return "lbm-pf-gfx950 0.2"; }
+
+int lbm_state_bytes(const lbm_params* p, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "null output");
+  *bytes = layout_of(*p).total;
+  return LBM_OK;
+}
 
 int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, void* state_dev,
              size_t state_bytes, void* stream, lbm_sim** out) {
@@ -552,13 +649,13 @@ int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, vo
 
 int lbm_step(lbm_sim* s, int n) {
   if (!s || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
-  if (n >= 2 && !s->graphs_ok) {
+  if (n >= 2 && !s->g_pair) {
     int rc = build_graphs(s);
     if (rc) return rc;
   }
   while (n > 0) {
     if (s->parity() == 1 || n == 1) {
-      HIPCHK(launch_step(s, s->parity(), s->stream));
+      HIPCHK(launch_step(s->ls, s->Q, s->ST, s->parity(), s->stream));
       s->steps += 1;
       n -= 1;
     } else if (s->g_many && n >= 2 * s->many_pairs) {
@@ -598,8 +695,7 @@ int lbm_reduce(lbm_sim* s, double* mass, double* kinetic) {
   hipLaunchKernelGGL(k_reduce_partial, dim3(s->nparts), dim3(256), 0, s->stream, s->K,
                      (const float*)s->out_buf(s->parity()), (const float*)s->u(), s->part);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s->stream, (const double*)s->part, s->nparts,
-                     s->res);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s->stream, (const double*)s->part, s->nparts, s->res);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(s->res_host, s->res, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
@@ -656,113 +752,36 @@ int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes) {
 
 int lbm_set_tile(lbm_sim* s, int bx, int by) {
   if (!s) return fail(LBM_EINVAL, "null handle");
-  const int t = bx * by;
-  if (bx < 16 || bx % 16 || by < 1 || (t != 64 && t != 128 && t != 256 && t != 512))
-    return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by in {64,128,256,512}");
-  s->T = tiling_of(s->P, bx, by);
-  s->TB = box_tiling(s->box, bx, by);
-  drop_graphs(s);
-  return LBM_OK;
+  if (!tile_ok(bx, by)) return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by in {64,128,256,512}");
+  return set_launch(s, bx, by, s->ls.bpc, s->ls.nt);
 }
 
 int lbm_set_store_hint(lbm_sim* s, int nontemporal) {
   if (!s) return fail(LBM_EINVAL, "null handle");
-  s->nt = nontemporal != 0;
-  drop_graphs(s);
-  return LBM_OK;
+  return set_launch(s, s->ls.bx, s->ls.by, s->ls.bpc, nontemporal ? 1 : 0);
+}
+
+int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu) {
+  if (!s || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad argument");
+  return set_launch(s, s->ls.bx, s->ls.by, blocks_per_cu, s->ls.nt);
 }
 
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by) {
   if (!s || !bx || !by) return fail(LBM_EINVAL, "null argument");
-  *bx = s->T.bx;
-  *by = s->T.by;
+  *bx = s->ls.bx;
+  *by = s->ls.by;
   return LBM_OK;
 }
 
 int lbm_kernel_times(lbm_sim* s, int n, double* out_ms) {
   if (!s || n < 1 || !out_ms) return fail(LBM_EINVAL, "bad argument");
-  const int K = 4;
-  hipEvent_t ev[4 * 64];
-  const int batch = std::min(n, 64);
-  for (int i = 0; i < K * batch; ++i) HIPCHK(hipEventCreate(&ev[i]));
-  double acc[3] = {0, 0, 0};
-  int done = 0;
-  int rc = LBM_OK;
-  while (done < n && rc == LBM_OK) {
-    const int m = std::min(batch, n - done);
-    for (int i = 0; i < m; ++i) {
-      hipError_t e = launch_step(s, s->parity(), s->stream, &ev[K * i]);
-      if (e != hipSuccess) {
-        rc = fail(LBM_EDEVICE, hipGetErrorString(e));
-        break;
-      }
-      s->steps += 1;
-    }
-    if (rc) break;
-    if (hipStreamSynchronize(s->stream) != hipSuccess) {
-      rc = fail(LBM_EDEVICE, "synchronize");
-      break;
-    }
-    for (int i = 0; i < m; ++i)
-      for (int k = 0; k < 3; ++k) {
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, ev[K * i + k], ev[K * i + k + 1]);
-        acc[k] += ms;
-      }
-    done += m;
-  }
-  for (int i = 0; i < K * batch; ++i) hipEventDestroy(ev[i]);
-  if (rc) return rc;
-  for (int k = 0; k < 3; ++k) out_ms[k] = acc[k] / n;
-  return LBM_OK;
+  return phase_times(s->ls, s->Q, s->ST, s->stream, s->steps, n, out_ms);
 }
-
-namespace {
-struct TuneEntry {
-  int bx, by, nt;
-  double ms;
-};
-std::mutex g_tune_mu;
-std::map<std::string, TuneEntry> g_tune_cache;
-
-std::string tune_key(const lbm_sim* s) {
-  char buf[160];
-  snprintf(buf, sizeof buf, "q%d st%d %dx%dx%d bc%d%d%d%d%d%d o%d i%d", s->Q, s->ST, s->P.nx, s->P.ny, s->P.nz,
-           s->P.bc[0], s->P.bc[1], s->P.bc[2], s->P.bc[3], s->P.bc[4], s->P.bc[5], s->K.has_outlet,
-           s->K.has_inlet);
-  return buf;
-}
-
-// mean ms per eager step over n steps (events around the whole step)
-int time_steps(lbm_sim* s, int n, double* ms) {
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, s->stream));
-  for (int i = 0; i < n; ++i) {
-    hipError_t e = launch_step(s, s->parity(), s->stream);
-    if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return fail(LBM_EDEVICE, hipGetErrorString(e));
-    }
-    s->steps += 1;
-  }
-  HIPCHK(hipEventRecord(e1, s->stream));
-  HIPCHK(hipEventSynchronize(e1));
-  float t = 0.f;
-  HIPCHK(hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  *ms = t / n;
-  return LBM_OK;
-}
-}  // namespace
 
 int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_out, double* ms_out) {
   if (!s || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
-  const std::string key = tune_key(s);
-  TuneEntry best = {s->T.bx, s->T.by, s->nt ? 1 : 0, 1e30};
+  const std::string key = params_key(s->P);
+  TuneEntry best = {s->ls.bx, s->ls.by, s->ls.bpc, s->ls.nt, 1e30};
   bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -773,30 +792,25 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
     }
   }
   if (!cached) {
-    static const int cand[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4},
-                                  {256, 2}, {32, 16}, {64, 2}, {128, 1}, {32, 4}, {16, 16}};
-    for (const auto& cb : cand) {
+    for (const auto& cb : kTiles) {
       const int bx = cb[0], by = cb[1];
-      if (bx > 16 && bx >= 2 * s->P.nx) continue;  // mostly idle lanes
+      if (bx > 16 && bx >= 2 * std::max(1, s->box.nx)) continue;  // mostly idle lanes
       if (by > 1 && by > s->P.ny) continue;
-      for (int nt = 0; nt < 2; ++nt) {
-        s->T = tiling_of(s->P, bx, by);
-        s->TB = box_tiling(s->box, bx, by);
-        s->nt = nt != 0;
-        double ms = 0.0;
-        int rc = time_steps(s, 2, &ms);  // warm-up
-        if (rc == LBM_OK) rc = time_steps(s, trial_steps, &ms);
-        if (rc) return rc;
-        if (ms < best.ms) best = {bx, by, nt, ms};
-      }
+      for (int bp : kBpc)
+        for (int nt = 0; nt < 2; ++nt) {
+          int rc = set_launch(s, bx, by, bp, nt);
+          double ms = 0.0;
+          if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, 2, &ms);  // warm-up
+          if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, trial_steps, &ms);
+          if (rc) return rc;
+          if (ms < best.ms) best = {bx, by, bp, nt, ms};
+        }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
-  s->T = tiling_of(s->P, best.bx, best.by);
-  s->TB = box_tiling(s->box, best.bx, best.by);
-  s->nt = best.nt != 0;
-  drop_graphs(s);
+  int rc = set_launch(s, best.bx, best.by, best.bpc, best.nt);
+  if (rc) return rc;
   if (bx_out) *bx_out = best.bx;
   if (by_out) *by_out = best.by;
   if (nt_out) *nt_out = best.nt;
@@ -807,10 +821,11 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
 void lbm_destroy(lbm_sim* s) {
   if (!s) return;
   drop_graphs(s);
-  if (s->part) hipFree(s->part);
-  if (s->res) hipFree(s->res);
-  if (s->res_host) hipHostFree(s->res_host);
-  if (s->cap) hipStreamDestroy(s->cap);
+  free_launch(s->ls);
+  if (s->part) (void)hipFree(s->part);
+  if (s->res) (void)hipFree(s->res);
+  if (s->res_host) (void)hipHostFree(s->res_host);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
   delete s;
 }
 
@@ -825,10 +840,7 @@ struct lbm_batch {
   std::vector<size_t> off;
   char* base = nullptr;
   hipStream_t stream = nullptr, cap = nullptr;
-  DomDev* d_dom = nullptr;
-  int* d_tile_dom = nullptr;
-  int ntiles = 0, nface = 0, nplane = 0;
-  int bx = 32, by = 8, bpc = 4, nt = 0, grid = 0, chunk = 1;
+  LaunchSet ls;
   long long steps = 0;
   hipGraphExec_t g_pair = nullptr;
   int* d_count = nullptr;
@@ -858,182 +870,18 @@ int batch_validate(int ndom, const lbm_params* p) {
   return LBM_OK;
 }
 
-void batch_drop_graph(lbm_batch* b) {
-  if (b->g_pair) hipGraphExecDestroy(b->g_pair);
-  b->g_pair = nullptr;
-}
-
-int batch_tables(lbm_batch* b) {
-  std::vector<DomDev> dom(b->ndom);
-  std::vector<int> tile_dom;
-  int tb = 0, fb = 0, pb = 0;
-  for (int d = 0; d < b->ndom; ++d) {
-    lbm_sim* v = b->views[d];
-    v->T = tiling_of(v->P, b->bx, b->by);
-    v->TB = box_tiling(v->box, b->bx, b->by);
-    v->nt = b->nt != 0;
-    DomDev& m = dom[d];
-    memset(&m, 0, sizeof m);
-    m.K = v->K;
-    for (int par = 0; par < 2; ++par) {
-      m.B[par] = v->bufs(par);
-      m.Bo[par] = v->bufs(par);
-      m.Bo[par].ref = v->out_buf(par);
-    }
-    m.X = v->box;
-    m.F = v->faces;
-    m.ntx = v->TB.ntx;
-    m.nty = v->TB.nty;
-    m.ntiles = v->TB.ntiles;
-    m.tile_base = tb;
-    m.face_base = fb;
-    m.plane_base = pb;
-    for (int t = 0; t < v->TB.ntiles; ++t) tile_dom.push_back(d);
-    tb += v->TB.ntiles;
-    fb += v->faces.n0 + v->faces.n1 + v->faces.n2;
-    pb += v->K.has_outlet ? v->K.plane : 0;
-  }
-  b->ntiles = tb;
-  b->nface = fb;
-  b->nplane = pb;
-  if (b->d_dom) hipFree(b->d_dom);
-  if (b->d_tile_dom) hipFree(b->d_tile_dom);
-  b->d_dom = nullptr;
-  b->d_tile_dom = nullptr;
-  HIPCHK(hipMalloc(&b->d_dom, sizeof(DomDev) * b->ndom));
-  HIPCHK(hipMalloc(&b->d_tile_dom, sizeof(int) * std::max(1, tb)));
-  HIPCHK(hipMemcpy(b->d_dom, dom.data(), sizeof(DomDev) * b->ndom, hipMemcpyHostToDevice));
-  if (tb) HIPCHK(hipMemcpy(b->d_tile_dom, tile_dom.data(), sizeof(int) * tb, hipMemcpyHostToDevice));
-  int dev = 0, cus = 256;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  b->grid = std::max(1, std::min(tb, cus * b->bpc));
-  b->chunk = std::max(1, (tb + b->grid - 1) / b->grid);
-  b->grid = std::max(1, (tb + b->chunk - 1) / b->chunk);
-  batch_drop_graph(b);
-  return LBM_OK;
-}
-
-template <int Q, int ST>
-hipError_t batch_launch_t(lbm_batch* b, int par, hipStream_t st, hipEvent_t* ev) {
-  const dim3 gi(b->grid), bi(b->bx * b->by);
-  const dim3 gf((b->nface + 255) / 256), bf(256);
-  if (ev) (void)hipEventRecord(ev[0], st);
-  if (b->ntiles) {
-    if (par == 0)
-      hipLaunchKernelGGL((kb_interior<Q, ST, 0, false, true>), gi, bi, 0, st, b->d_dom, b->d_tile_dom, b->ntiles,
-                         b->chunk, b->bx, b->by);
-    else
-      hipLaunchKernelGGL((kb_interior<Q, ST, 1, false, true>), gi, bi, 0, st, b->d_dom, b->d_tile_dom, b->ntiles,
-                         b->chunk, b->bx, b->by);
-  }
-  if (b->nface) {
-    if (par == 0)
-      hipLaunchKernelGGL((kb_faces<Q, ST, 0, false, true>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);
-    else
-      hipLaunchKernelGGL((kb_faces<Q, ST, 1, false, true>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);
-  }
-  if (ev) (void)hipEventRecord(ev[1], st);
-#define KB_STEP(PAR, NTV)                                                                                  \
-  do {                                                                                                     \
-    if (b->ntiles)                                                                                         \
-      hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NTV, false>), gi, bi, 0, st, b->d_dom, b->d_tile_dom,    \
-                         b->ntiles, b->chunk, b->bx, b->by);                                               \
-    if (b->nface)                                                                                          \
-      hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NTV, false>), gf, bf, 0, st, b->d_dom, b->ndom, b->nface);  \
-  } while (0)
-  if (par == 0) {
-    if (b->nt)
-      KB_STEP(0, true);
-    else
-      KB_STEP(0, false);
-  } else {
-    if (b->nt)
-      KB_STEP(1, true);
-    else
-      KB_STEP(1, false);
-  }
-#undef KB_STEP
-  if (ev) (void)hipEventRecord(ev[2], st);
-  if (b->nplane) {
-    const dim3 gp((b->nplane + 255) / 256), bp(256);
-    if (par == 0)
-      hipLaunchKernelGGL((kb_outlet<Q, ST, 0>), gp, bp, 0, st, b->d_dom, b->ndom, b->nplane);
-    else
-      hipLaunchKernelGGL((kb_outlet<Q, ST, 1>), gp, bp, 0, st, b->d_dom, b->ndom, b->nplane);
-  }
-  if (ev) (void)hipEventRecord(ev[3], st);
-  return hipGetLastError();
-}
-
-hipError_t batch_launch(lbm_batch* b, int par, hipStream_t st, hipEvent_t* ev = nullptr) {
-  if (b->Q == 9) {
-    switch (b->ST) {
-      case 0: return batch_launch_t<9, 0>(b, par, st, ev);
-      case 1: return batch_launch_t<9, 1>(b, par, st, ev);
-      default: return batch_launch_t<9, 2>(b, par, st, ev);
-    }
-  }
-  switch (b->ST) {
-    case 0: return batch_launch_t<19, 0>(b, par, st, ev);
-    case 1: return batch_launch_t<19, 1>(b, par, st, ev);
-    default: return batch_launch_t<19, 2>(b, par, st, ev);
-  }
-}
-
-int batch_graph(lbm_batch* b) {
-  batch_drop_graph(b);
-  hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  hipError_t err = batch_launch(b, 0, b->cap);
-  if (err == hipSuccess) err = batch_launch(b, 1, b->cap);
-  hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
-  if (err != hipSuccess || e2 != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
-    return fail(LBM_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
-  }
-  hipError_t e3 = hipGraphInstantiate(&b->g_pair, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
-  if (e3 != hipSuccess) return fail(LBM_EDEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e3));
-  return LBM_OK;
+int batch_set_launch(lbm_batch* b, int bx, int by, int bpc, int nt) {
+  drop_graph(b->g_pair);
+  return build_launch(b->ls, b->views.data(), b->ndom, bx, by, bpc, nt);
 }
 
 void batch_sync_views(lbm_batch* b) {
   for (auto* v : b->views) v->steps = b->steps;
 }
 
-int batch_time_steps(lbm_batch* b, int n, double* ms) {
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventRecord(e0, b->stream));
-  for (int i = 0; i < n; ++i) {
-    hipError_t e = batch_launch(b, (int)(b->steps & 1), b->stream);
-    if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      return fail(LBM_EDEVICE, hipGetErrorString(e));
-    }
-    b->steps += 1;
-  }
-  HIPCHK(hipEventRecord(e1, b->stream));
-  HIPCHK(hipEventSynchronize(e1));
-  float t = 0.f;
-  HIPCHK(hipEventElapsedTime(&t, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  *ms = t / n;
-  return LBM_OK;
-}
-
-std::mutex g_btune_mu;
-std::map<std::string, TuneEntry> g_btune_cache;
-std::map<std::string, int> g_btune_bpc;
-
 std::string batch_key(const lbm_batch* b) {
-  std::string k = "q" + std::to_string(b->Q) + " st" + std::to_string(b->ST) + " n" + std::to_string(b->ndom);
-  for (auto* v : b->views)
-    k += " " + std::to_string(v->P.nx) + "x" + std::to_string(v->P.ny) + "x" + std::to_string(v->P.nz);
+  std::string k = "batch n" + std::to_string(b->ndom);
+  for (auto* v : b->views) k += " " + params_key(v->P);
   return k;
 }
 
@@ -1078,7 +926,7 @@ int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, 
   }
   if (rc == LBM_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
     rc = fail(LBM_EDEVICE, "stream create");
-  if (rc == LBM_OK) rc = batch_tables(b);
+  if (rc == LBM_OK) rc = batch_set_launch(b, 32, 8, 4, 0);
   if (rc) {
     lbm_batch_destroy(b);
     return rc;
@@ -1090,12 +938,12 @@ int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, 
 int lbm_batch_step(lbm_batch* b, int n) {
   if (!b || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
   if (n >= 2 && !b->g_pair) {
-    int rc = batch_graph(b);
+    int rc = capture_pairs(b->ls, b->Q, b->ST, b->cap, 1, &b->g_pair);
     if (rc) return rc;
   }
   while (n > 0) {
     if ((b->steps & 1) || n == 1) {
-      HIPCHK(batch_launch(b, (int)(b->steps & 1), b->stream));
+      HIPCHK(launch_step(b->ls, b->Q, b->ST, (int)(b->steps & 1), b->stream));
       b->steps += 1;
       n -= 1;
     } else {
@@ -1115,8 +963,10 @@ int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic) {
   int worst = LBM_OK;
   for (int d = 0; d < b->ndom; ++d) {
     int rc = lbm_reduce(b->views[d], &mass[d], &kinetic[d]);
-    if (rc == LBM_EUNSTABLE) worst = rc;
-    else if (rc) return rc;
+    if (rc == LBM_EUNSTABLE)
+      worst = rc;
+    else if (rc)
+      return rc;
   }
   if (worst) return fail(worst, "non-finite mass or kinetic energy in a domain");
   return LBM_OK;
@@ -1140,7 +990,7 @@ int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length) {
   int maxz = 0;
   for (auto* v : b->views) maxz = std::max(maxz, v->Q == 9 ? v->P.ny : v->P.nz);
   if (maxz > b->count_cap) {
-    if (b->d_count) hipFree(b->d_count);
+    if (b->d_count) (void)hipFree(b->d_count);
     b->d_count = nullptr;
     HIPCHK(hipMalloc(&b->d_count, sizeof(int) * maxz));
     b->count_cap = maxz;
@@ -1168,58 +1018,47 @@ int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length) {
 
 int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal) {
   if (!b) return fail(LBM_EINVAL, "null handle");
-  const int t = bx * by;
-  if (bx < 16 || bx % 16 || by < 1 || (t != 64 && t != 128 && t != 256 && t != 512) || blocks_per_cu < 1 ||
-      blocks_per_cu > 64)
-    return fail(LBM_EINVAL, "bad launch shape");
-  b->bx = bx;
-  b->by = by;
-  b->bpc = blocks_per_cu;
-  b->nt = nontemporal ? 1 : 0;
-  return batch_tables(b);
+  if (!tile_ok(bx, by) || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad launch shape");
+  return batch_set_launch(b, bx, by, blocks_per_cu, nontemporal ? 1 : 0);
 }
 
 int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blocks_per_cu, int* nontemporal,
                        double* ms_per_step) {
   if (!b || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
   const std::string key = batch_key(b);
-  TuneEntry best = {b->bx, b->by, b->nt, 1e30};
-  int best_bpc = b->bpc;
+  TuneEntry best = {b->ls.bx, b->ls.by, b->ls.bpc, b->ls.nt, 1e30};
   bool cached = false;
   {
-    std::lock_guard<std::mutex> lk(g_btune_mu);
-    auto it = g_btune_cache.find(key);
-    if (it != g_btune_cache.end()) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
       best = it->second;
-      best_bpc = g_btune_bpc[key];
       cached = true;
     }
   }
   if (!cached) {
-    static const int cand[][2] = {{32, 8}, {32, 4}, {64, 4}, {16, 16}, {32, 16}, {64, 2}, {16, 8}};
-    static const int bpcs[] = {2, 4, 8};
-    for (const auto& cb : cand)
-      for (int bp : bpcs)
+    int minx = 1 << 30;
+    for (auto* v : b->views) minx = std::min(minx, std::max(1, v->box.nx));
+    for (const auto& cb : kTiles) {
+      if (cb[0] > 16 && cb[0] >= 2 * minx) continue;
+      for (int bp : kBpc)
         for (int nt = 0; nt < 2; ++nt) {
-          int rc = lbm_batch_set_launch(b, cb[0], cb[1], bp, nt);
+          int rc = batch_set_launch(b, cb[0], cb[1], bp, nt);
           double ms = 0.0;
-          if (rc == LBM_OK) rc = batch_time_steps(b, 2, &ms);
-          if (rc == LBM_OK) rc = batch_time_steps(b, trial_steps, &ms);
+          if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, 2, &ms);
+          if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, trial_steps, &ms);
           if (rc) return rc;
-          if (ms < best.ms) {
-            best = {cb[0], cb[1], nt, ms};
-            best_bpc = bp;
-          }
+          if (ms < best.ms) best = {cb[0], cb[1], bp, nt, ms};
         }
-    std::lock_guard<std::mutex> lk(g_btune_mu);
-    g_btune_cache[key] = best;
-    g_btune_bpc[key] = best_bpc;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
   }
-  int rc = lbm_batch_set_launch(b, best.bx, best.by, best_bpc, best.nt);
+  int rc = batch_set_launch(b, best.bx, best.by, best.bpc, best.nt);
   if (rc) return rc;
   if (bx) *bx = best.bx;
   if (by) *by = best.by;
-  if (blocks_per_cu) *blocks_per_cu = best_bpc;
+  if (blocks_per_cu) *blocks_per_cu = best.bpc;
   if (nontemporal) *nontemporal = best.nt;
   if (ms_per_step) *ms_per_step = best.ms;
   return LBM_OK;
@@ -1227,34 +1066,17 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blo
 
 int lbm_batch_kernel_times(lbm_batch* b, int n, double* out_ms) {
   if (!b || n < 1 || !out_ms) return fail(LBM_EINVAL, "bad argument");
-  hipEvent_t ev[4];
-  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  double acc[3] = {0, 0, 0};
-  for (int i = 0; i < n; ++i) {
-    hipError_t e = batch_launch(b, (int)(b->steps & 1), b->stream, ev);
-    if (e != hipSuccess) return fail(LBM_EDEVICE, hipGetErrorString(e));
-    b->steps += 1;
-    HIPCHK(hipStreamSynchronize(b->stream));
-    for (int k = 0; k < 3; ++k) {
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-      acc[k] += ms;
-    }
-  }
-  for (auto& e : ev) hipEventDestroy(e);
-  for (int k = 0; k < 3; ++k) out_ms[k] = acc[k] / n;
-  return LBM_OK;
+  return phase_times(b->ls, b->Q, b->ST, b->stream, b->steps, n, out_ms);
 }
 
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
-  batch_drop_graph(b);
+  drop_graph(b->g_pair);
+  free_launch(b->ls);
   for (auto* v : b->views)
     if (v) lbm_destroy(v);
-  if (b->d_dom) hipFree(b->d_dom);
-  if (b->d_tile_dom) hipFree(b->d_tile_dom);
-  if (b->d_count) hipFree(b->d_count);
-  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->d_count) (void)hipFree(b->d_count);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
 

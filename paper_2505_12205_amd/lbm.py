@@ -65,6 +65,7 @@ def _load():
     L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
     L.lbm_set_store_hint.argtypes = [vp, C.c_int]
+    L.lbm_set_blocks_per_cu.argtypes = [vp, C.c_int]
     L.lbm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.lbm_destroy.argtypes = [vp]
@@ -91,7 +92,7 @@ lib = _load()
 
 EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fields", "lbm_reduce",
             "lbm_export_state", "lbm_import_state", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
-            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_autotune",
+            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_blocks_per_cu", "lbm_autotune",
             "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version",
             "lbm_batch_state_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_steps_done",
             "lbm_batch_reduce", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
@@ -246,6 +247,10 @@ class Sim:
 
     def set_store_hint(self, nontemporal: bool):
         _check(lib.lbm_set_store_hint(self._h, 1 if nontemporal else 0))
+        return self
+
+    def set_blocks_per_cu(self, n: int):
+        _check(lib.lbm_set_blocks_per_cu(self._h, int(n)))
         return self
 
     def autotune(self, trial_steps: int = 10):
