@@ -104,7 +104,8 @@ int lbm_state_bytes(const lbm_params* p, size_t* bytes);
 
 /* Create a simulation on the caller's buffer and stream.
  *   phi0_dev  initial phase field [N] (required)
- *   u0_dev    initial velocity [3N] or NULL for rest
+ *   u0_dev    initial velocity [3N] or NULL for rest (D2Q9: the third
+ *             component is ignored)
  *   state_dev caller-allocated device buffer of at least lbm_state_bytes();
  *             it must outlive the handle and is not freed by the library
  *   stream    hipStream_t (NULL = default stream)
@@ -146,7 +147,7 @@ int lbm_save(lbm_sim* s, void* host_buf, size_t bytes);
 int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes);
 
 /* Launch shape of the fused kernel: threads per block along x and y
- * (bx * by must be 64, 128, 256 or 512; bx a multiple of 16). */
+ * (bx a multiple of 16, bx * by a multiple of 64 up to 512). */
 int lbm_set_tile(lbm_sim* s, int bx, int by);
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by);
 

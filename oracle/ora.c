@@ -828,7 +828,10 @@ int ora_init(ora_sim* s, const double* phi0, const double* u0) {
   ctx_full(s, &c);
   memcpy(s->phi, phi0, sizeof(double) * N);
   c.phi = s->phi;
-  for (long i = 0; i < 3 * N; ++i) s->u[i] = u0 ? u0[i] : 0.0;
+  /* the D2Q9 velocity set (appendix A) has no z component: a third
+     component of the initial velocity is dropped in 2D */
+  const long nu = (L->q == 9) ? 2 * N : 3 * N;
+  for (long i = 0; i < 3 * N; ++i) s->u[i] = (u0 && i < nu) ? u0[i] : 0.0;
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < N; ++i) {
     int x[3];

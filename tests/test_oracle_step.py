@@ -369,3 +369,17 @@ def test_freeslip_channel_uniform_tangential_flow_is_fixed_point():
     h, g, uu = o.state()
     assert np.abs(h - h0).max() < 1e-15 and np.abs(g - g0).max() < 1e-15
     assert np.abs(uu[0]).max() < 1e-17
+
+
+def test_2d_initial_velocity_has_no_z_component():
+    """D2Q9 has no z velocity: a third component of u0 changes nothing."""
+    cfg, phi0, _ = W.drop2d(n=16, radius=5.0)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((3,) + phi0.shape) * 1e-3
+    u2 = u.copy()
+    u2[2] = 0.0
+    a = oracle.Oracle(cfg).init(phi0, u).step(3)
+    b = oracle.Oracle(cfg).init(phi0, u2).step(3)
+    ha, ga, ua = a.state()
+    hb, gb, ub = b.state()
+    assert np.array_equal(ha, hb) and np.array_equal(ga, gb) and np.array_equal(ua, ub)
