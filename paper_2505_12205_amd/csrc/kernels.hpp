@@ -5,8 +5,9 @@
 //   kb_interior<P, STEP>, kb_faces<P, STEP>: stencil of phi, macroscopic update,
 //       both collisions and the in-place AA streaming of both population sets
 //   kb_outlet<P>: convective outflow plane (only with an outlet face)
-// Interior nodes (away from the faces of non-periodic axes) take the fast
-// path with precomputed neighbour offsets; face-layer nodes the general path.
+// Nodes off the y and z faces of non-periodic axes take the tiled fast path
+// with precomputed neighbour offsets (x walls included, with a per-lane slot
+// choice); the y and z face layers take the general path.
 //
 // Storage is structure-of-arrays, pop[a][node] with node = x + nx*(y + ny*z)
 // (x fastest), one array per set; streaming is the AA pattern:
@@ -39,6 +40,7 @@ struct KParams {
   float in_c0, in_c1, in_R, in_u, two_over_xi;
   int clamp;
   int has_inlet, has_outlet;
+  int wbits, nsbits;       // x faces: bit 0 (1) = the minus (plus) face is a wall / a no-slip wall
 };
 
 struct KBufs {
@@ -660,20 +662,61 @@ struct Nbr {
   }
 };
 
+// Neighbour offsets of node c: periodic faces wrap; across a wall face the
+// offset is clamped to the node itself (the ghost rule of the phase-field
+// stencil, and the tangential neighbour of a reflected population).
 __device__ __forceinline__ Nbr make_nbr(const KParams& P, const int c[3]) {
   Nbr n;
   n.node = node_of(P, c[0], c[1], c[2]);
   const int sxy = P.nx * P.ny;
-  n.ox[0] = c[0] == 0 ? P.nx - 1 : -1;
+  const bool px = P.bc[0] == BC_PERIODIC, py = P.bc[2] == BC_PERIODIC, pz = P.bc[4] == BC_PERIODIC;
+  n.ox[0] = c[0] == 0 ? (px ? P.nx - 1 : 0) : -1;
   n.ox[1] = 0;
-  n.ox[2] = c[0] == P.nx - 1 ? 1 - P.nx : 1;
-  n.oy[0] = c[1] == 0 ? (P.ny - 1) * P.nx : -P.nx;
+  n.ox[2] = c[0] == P.nx - 1 ? (px ? 1 - P.nx : 0) : 1;
+  n.oy[0] = c[1] == 0 ? (py ? (P.ny - 1) * P.nx : 0) : -P.nx;
   n.oy[1] = 0;
-  n.oy[2] = c[1] == P.ny - 1 ? (1 - P.ny) * P.nx : P.nx;
-  n.oz[0] = c[2] == 0 ? (P.nz - 1) * sxy : -sxy;
+  n.oy[2] = c[1] == P.ny - 1 ? (py ? (1 - P.ny) * P.nx : 0) : P.nx;
+  n.oz[0] = c[2] == 0 ? (pz ? (P.nz - 1) * sxy : 0) : -sxy;
   n.oz[1] = 0;
-  n.oz[2] = c[2] == P.nz - 1 ? (1 - P.nz) * sxy : sxy;
+  n.oz[2] = c[2] == P.nz - 1 ? (pz ? (1 - P.nz) * sxy : 0) : sxy;
   return n;
+}
+
+// Walls of the x axis are handled inside the tiled kernels: their nodes are
+// one per row, so a separate face launch would read and write them one value
+// per memory line.  Bit 0 (1) of the result: node c lies on the minus (plus)
+// x face and that face is a wall.
+__device__ __forceinline__ int wall_lane(const KParams& P, const int c[3]) {
+  return ((c[0] == 0 ? 1 : 0) | (c[0] == P.nx - 1 ? 2 : 0)) & P.wbits;
+}
+
+// true if c + e_t lies beyond an x wall, for a node with wall bits `on`
+template <int Q>
+__device__ __forceinline__ bool wall_hit(int on, int t) {
+  const int e = Lat<Q>::ex[t];
+  return e != 0 && ((on >> (e > 0 ? 1 : 0)) & 1);
+}
+
+// Slot (population index, node) that receives post-collision population t
+// of node nb.node -- the slot that t's opposite was read from -- and the node
+// that reads the slot at the next step.  Even steps: pop[tbar][x]; odd steps:
+// pop[t][x + e_t].  On an x-wall lane (WALL) a target beyond the wall becomes
+// the x-reflected population of the tangential neighbour (free slip) or
+// pop[tbar] of the node itself (no slip), as in the general path.
+template <int Q, int ODD, bool WALL>
+__device__ __forceinline__ void slot_of(const Nbr& nb, int on, int onns, int t, int& pop, int& nd, int& rdr) {
+  rdr = nb.at<Q>(t);
+  pop = ODD ? t : Lat<Q>::opp[t];
+  nd = ODD ? rdr : nb.node;
+  if (!WALL) return;
+  if (ODD && wall_hit<Q>(on, t)) pop = reflect<Q>(t, 1);
+  if (wall_hit<Q>(onns, t)) {
+    rdr = nb.node;
+    if (ODD) {
+      pop = Lat<Q>::opp[t];
+      nd = nb.node;
+    }
+  }
 }
 
 // true if the node touches a face whose boundary is not periodic
@@ -698,7 +741,7 @@ __device__ __forceinline__ bool on_special_face(const KParams& P, const int c[3]
 // sum to 1 + O(1e-8)) would leave a small systematic mass drift per step, so
 // the node's mass is restored on the rest population with compensated sums
 // (a zero correction in exact arithmetic).
-template <int Q, int ST, int ODD, bool NT>
+template <int Q, int ST, int ODD, bool NT, bool WALL>
 __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, const int c[3]) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -706,6 +749,8 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   using Ty = typename C::T;
   const Nbr nb = make_nbr(P, c);
   const int node = nb.node;
+  const int on = WALL ? wall_lane(P, c) : 0;
+  const int onns = on & P.nsbits;
   const unsigned N = (unsigned)P.N;
   Ty* Gp = (Ty*)B.g;  // loads and stores go through one pointer: in place
   Ty* Hp = (Ty*)B.h;
@@ -719,12 +764,21 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   gr[2] *= 3.0f;
   lap *= 6.0f;
 
-  // Population a is read from slot (ra_pop, ra_idx) and its post-collision
-  // value goes to the slot abar was read from.  Slots are addressed as a
-  // uniform per-population base plus a 32-bit node index.
-  auto rpop = [&](int a) -> int { return ODD ? L::opp[a] : a; };
-  auto ridx = [&](int a) -> unsigned { return ODD ? (unsigned)nb.at<Q>(L::opp[a]) : (unsigned)node; };
+  // Population a is read from the slot of abar (slot_of) and its
+  // post-collision value goes to the slot abar was read from.  Slots are
+  // addressed as a per-population base (uniform away from wall lanes) plus a
+  // 32-bit node index.
   const size_t NN = (size_t)P.N;
+  // On wall lanes the slot's population differs from the uniform one by at
+  // most 3 (x reflection) or 1 (bounce-back), so the per-lane part stays a
+  // signed 32-bit index (|index| < 4N < 2^31 for every admissible grid).
+  auto sbase = [&](int t, int& idx, int& rdr) -> size_t {
+    int pop, nd;
+    slot_of<Q, ODD, WALL>(nb, on, onns, t, pop, nd, rdr);
+    const int pop0 = ODD ? t : L::opp[t];
+    idx = WALL ? nd + (pop - pop0) * (int)P.N : nd;
+    return (size_t)pop0 * NN;
+  };
 
   // hydrodynamic moments, opposite pairs summed and differenced
   float g0 = C::ld_g(Gp, (unsigned)node, L::w[0]);
@@ -734,8 +788,12 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   for (int a = 1; a < Q; ++a) {
     const int b = L::opp[a];
     if (b < a) continue;
-    const float ga = C::ld_g(Gp + rpop(a) * NN, ridx(a), L::w[a]);
-    const float gb = C::ld_g(Gp + rpop(b) * NN, ridx(b), L::w[b]);
+    int ia, ib;
+    int ra, rb;
+    const Ty* Ga = Gp + sbase(b, ia, ra);
+    const Ty* Gb = Gp + sbase(a, ib, rb);
+    const float ga = C::ld_g(Ga, ia, L::w[a]);
+    const float gb = C::ld_g(Gb, ib, L::w[b]);
     const float s = ga + gb, d = ga - gb;
     p += s;
     if (L::ex[a]) { j[0] += L::ex[a] * d; S.xx += s; }
@@ -780,11 +838,14 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     if (b < a) continue;
     const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
     const float w = L::w[a];
-    Ty* Ha = Hp + rpop(a) * NN;
-    Ty* Hb = Hp + rpop(b) * NN;
-    Ty* Ga = Gp + rpop(a) * NN;
-    Ty* Gb = Gp + rpop(b) * NN;
-    const unsigned ia = ridx(a), ib = ridx(b);
+    int ia, ib;
+    int rdr_b, rdr_a;  // readers of the slots of a's and b's post-collision values
+    const size_t oa = sbase(b, ia, rdr_b);  // a is read here, b's post value goes here
+    const size_t ob = sbase(a, ib, rdr_a);
+    Ty* Ha = Hp + oa;
+    Ty* Hb = Hp + ob;
+    Ty* Ga = Gp + oa;
+    Ty* Gb = Gp + ob;
     const float ha = C::ld_h(Ha, ia, w, ref);
     const float hb = C::ld_h(Hb, ib, w, ref);
     const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
@@ -811,8 +872,8 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const float da = om * (hsym + hanti - ha) + fphi;
     const float db = om * (hsym - hanti - hb) - fphi;
     dsum += da + db;
-    const float wra = (ST == 0) ? 0.0f : B.phi[nb.at<Q>(a)];  // readers' phase field
-    const float wrb = (ST == 0) ? 0.0f : B.phi[nb.at<Q>(b)];
+    const float wra = (ST == 0) ? 0.0f : B.phi[rdr_a];  // readers' phase field
+    const float wrb = (ST == 0) ? 0.0f : B.phi[rdr_b];
     C::template st_h<NT>(Hb, ib, ha + da, 1.0f / w, wra);
     C::template st_h<NT>(Ha, ia, hb + db, 1.0f / w, wrb);
   }
@@ -888,8 +949,8 @@ __device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, c
   }
 }
 
-// Interior box: every axis whose faces are not periodic loses its two face
-// layers; the tiling covers the box.
+// Tiled box: the whole grid less the face layers of non-periodic y and z axes
+// (x walls stay in the box as wall lanes).
 struct Box {
   int x0, y0, z0, nx, ny, nz;  // origin and extent
 };
@@ -911,57 +972,65 @@ __device__ __forceinline__ bool box_coords(const Box& X, const Tiling& T, int c[
   return tile_node(X, T, xcd_remap(blockIdx.x, gridDim.x), (int)threadIdx.x, c);
 }
 
-// Face layers of non-periodic axes, enumerated slab by slab without overlap:
-// axis 0 faces (whole y-z planes), then axis 1 faces inside the x range left,
-// then axis 2 faces inside the x-y range left.
+// Face layers (general path), enumerated without overlap and with x fastest
+// so that a wave covers contiguous nodes: in 3D the y = 0 and y = ny-1 rows
+// of the box's z range (non-periodic y), then the two planes of the last
+// axis (non-periodic z in 3D, y in 2D), minus side first.
 struct Faces {
-  int n0, n1, n2;          // nodes in each slab (0 if the axis is periodic)
-  int x0, nxi, y0, nyi;    // interior x / y ranges used by later slabs
+  int n1, n2;    // nodes of the y rows (3D) and of the last-axis planes
+  int z0, nzb;   // z range of the y rows
 };
 
+template <int Q>
 __device__ __forceinline__ void face_coords(const KParams& P, const Faces& F, int t, int c[3]) {
-  if (t < F.n0) {  // x = 0 or nx-1, all y, z
-    const int side = t & 1, r = t >> 1;
-    c[0] = side ? P.nx - 1 : 0;
-    c[1] = r % P.ny;
-    c[2] = r / P.ny;
-    return;
-  }
-  t -= F.n0;
-  if (t < F.n1) {  // y = 0 or ny-1
-    const int side = t & 1, r = t >> 1;
+  if (Lat<Q>::D == 3 && t < F.n1) {
+    const int half = F.n1 >> 1;
+    const int side = t >= half ? 1 : 0;
+    const int r = t - side * half;
+    c[0] = r % P.nx;
     c[1] = side ? P.ny - 1 : 0;
-    c[0] = F.x0 + r % F.nxi;
-    c[2] = r / F.nxi;
+    c[2] = F.z0 + r / P.nx;
     return;
   }
-  t -= F.n1;  // z = 0 or nz-1
-  const int side = t & 1, r = t >> 1;
-  c[2] = side ? P.nz - 1 : 0;
-  c[0] = F.x0 + r % F.nxi;
-  c[1] = F.y0 + r / F.nxi;
+  t -= F.n1;
+  const int side = t >= P.plane ? 1 : 0;
+  const int r = t - side * P.plane;
+  if (Lat<Q>::D == 3) {
+    c[0] = r % P.nx;
+    c[1] = r / P.nx;
+    c[2] = side ? P.nz - 1 : 0;
+  } else {
+    c[0] = r;
+    c[1] = side ? P.ny - 1 : 0;
+    c[2] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // phase field phi = sum_a h_a of the current state (Eq. phase_field_variable),
 // compensated sum; interior nodes and face-layer nodes
 // ---------------------------------------------------------------------------
-template <int Q, int ST, int ODD>
+template <int Q, int ST, int ODD, bool WALL>
 __device__ __forceinline__ void phi_fast(const KParams& P, const KBufs& B, const int c[3]) {
   using L = Lat<Q>;
   using C = Codec<ST>;
   using Ty = typename C::T;
   const Nbr nb = make_nbr(P, c);
   const int node = nb.node;
+  const int on = WALL ? wall_lane(P, c) : 0;
+  const int onns = on & P.nsbits;
   const size_t NN = (size_t)P.N;
   const Ty* Hp = (const Ty*)B.h;
   const float ref = (ST == 0) ? 0.0f : B.ref[node];
   float s = 0.0f, cc = 0.0f;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
-    const int pop = ODD ? L::opp[a] : a;
-    const unsigned idx = ODD ? (unsigned)nb.at<Q>(L::opp[a]) : (unsigned)node;
-    kahan_add(C::ld_h(Hp + pop * NN, idx, L::w[a], ref), s, cc);
+    int pop, nd, rdr;
+    const int t = L::opp[a];  // a is read from the slot of abar
+    slot_of<Q, ODD, WALL>(nb, on, onns, t, pop, nd, rdr);
+    const int pop0 = ODD ? t : a;
+    const int idx = WALL ? nd + (pop - pop0) * P.N : nd;
+    kahan_add(C::ld_h(Hp + (size_t)pop0 * NN, idx, L::w[a], ref), s, cc);
   }
   B.phi_out[node] = s - cc;
 }
@@ -1031,7 +1100,7 @@ struct DomDev {
 // Persistent, chunked launch over the tile list of all domains: each block
 // walks a contiguous chunk of tiles (contiguous per XCD after the remap), so
 // neighbouring tiles of one domain share an L2.
-template <int Q, int ST, int ODD, bool NT, bool PHI>
+template <int Q, int ST, int ODD, bool NT, bool PHI, bool WALL>
 __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D, const int* __restrict__ tile_dom,
                                                    int ntiles, int chunk, int bx, int by) {
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -1049,9 +1118,9 @@ __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D,
     int c[3];
     if (!tile_node(dm.X, T, t - dm.tile_base, (int)threadIdx.x, c)) continue;
     if (PHI)
-      phi_fast<Q, ST, ODD>(dm.K, dm.B[ODD], c);
+      phi_fast<Q, ST, ODD, WALL>(dm.K, dm.B[ODD], c);
     else
-      step_fast<Q, ST, ODD, NT>(dm.K, dm.B[ODD], c);
+      step_fast<Q, ST, ODD, NT, WALL>(dm.K, dm.B[ODD], c);
   }
 }
 
@@ -1075,7 +1144,7 @@ __global__ __launch_bounds__(256) void kb_faces(const DomDev* __restrict__ D, in
   const int d = find_dom<0>(D, ndom, t);
   const DomDev& dm = D[d];
   int c[3];
-  face_coords(dm.K, dm.F, t - dm.face_base, c);
+  face_coords<Q>(dm.K, dm.F, t - dm.face_base, c);
   if (PHI)
     phi_general<Q, ST, ODD>(dm.K, dm.B[ODD], c);
   else

@@ -144,6 +144,11 @@ KParams kparams_of(const lbm_params& p) {
   K.clamp = (p.variant_flags & LBM_VF_CLAMP_PHI) ? 1 : 0;
   K.has_inlet = has_bc(p, LBM_BC_VELOCITY_INLET) ? 1 : 0;
   K.has_outlet = has_bc(p, LBM_BC_CONVECTIVE_OUTLET) ? 1 : 0;
+  for (int side = 0; side < 2; ++side) {  // x faces (never inlet or outlet)
+    const int b = p.bc[side];
+    if (b == LBM_BC_NOSLIP || b == LBM_BC_FREESLIP) K.wbits |= 1 << side;
+    if (b == LBM_BC_NOSLIP) K.nsbits |= 1 << side;
+  }
   return K;
 }
 
@@ -162,14 +167,15 @@ bool axis_periodic(const lbm_params& p, int d) {
   return d >= ndim || p.bc[2 * d] == LBM_BC_PERIODIC;
 }
 
-// interior box (fast path) and the face slabs around it (general path)
+// tiled box (fast path: everything but the face layers of non-periodic y
+// and z axes; x walls are wall lanes) and those face layers (general path)
 void split_domain(const lbm_params& p, Box& X, Faces& F) {
   const int n[3] = {p.nx, p.ny, p.nz};
   int o[3], e[3];
   for (int d = 0; d < 3; ++d) {
-    const bool per = axis_periodic(p, d);
-    o[d] = per ? 0 : 1;
-    e[d] = per ? n[d] : std::max(0, n[d] - 2);
+    const bool cut = d > 0 && !axis_periodic(p, d);
+    o[d] = cut ? 1 : 0;
+    e[d] = cut ? std::max(0, n[d] - 2) : n[d];
   }
   X.x0 = o[0];
   X.y0 = o[1];
@@ -177,13 +183,12 @@ void split_domain(const lbm_params& p, Box& X, Faces& F) {
   X.nx = e[0];
   X.ny = e[1];
   X.nz = e[2];
-  F.n0 = axis_periodic(p, 0) ? 0 : 2 * p.ny * p.nz;
-  F.x0 = o[0];
-  F.nxi = e[0];
-  F.n1 = axis_periodic(p, 1) ? 0 : 2 * e[0] * p.nz;
-  F.y0 = o[1];
-  F.nyi = e[1];
-  F.n2 = axis_periodic(p, 2) ? 0 : 2 * e[0] * e[1];
+  const bool d3 = p.lattice == LBM_D3Q19;
+  F.z0 = o[2];
+  F.nzb = e[2];
+  F.n1 = (d3 && !axis_periodic(p, 1)) ? 2 * p.nx * e[2] : 0;
+  const int last = d3 ? 2 : 1;
+  F.n2 = axis_periodic(p, last) ? 0 : 2 * plane_of(p);
 }
 
 void default_tile(const lbm_params& p, int& bx, int& by) {
@@ -198,7 +203,7 @@ void default_tile(const lbm_params& p, int& bx, int& by) {
 
 bool tile_ok(int bx, int by) {
   const int t = bx * by;
-  return bx >= 16 && bx % 16 == 0 && by >= 1 && (t == 64 || t == 128 || t == 256 || t == 512);
+  return bx >= 16 && bx % 16 == 0 && by >= 1 && t % 64 == 0 && t <= 512;
 }
 
 // device table and launch geometry of a set of domains
@@ -207,6 +212,7 @@ struct LaunchSet {
   int* d_tile = nullptr;  // tile -> domain (null for a single domain)
   int ndom = 0, ntiles = 0, nface = 0, nplane = 0;
   int bx = 64, by = 4, bpc = 4, nt = 0;
+  bool wall = false;  // some domain has lateral wall faces (wall lanes in the tiles)
   int grid = 1, chunk = 1;
 };
 
@@ -270,6 +276,7 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   std::vector<DomDev> dom(n);
   std::vector<int> tile_dom;
   int tb = 0, fb = 0, pb = 0;
+  bool wall = false;
   for (int d = 0; d < n; ++d) {
     lbm_sim* s = v[d];
     DomDev& m = dom[d];
@@ -291,10 +298,12 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
     m.plane_base = pb;
     if (n > 1) tile_dom.insert(tile_dom.end(), (size_t)TB.ntiles, d);
     tb += TB.ntiles;
-    fb += s->faces.n0 + s->faces.n1 + s->faces.n2;
+    fb += s->faces.n1 + s->faces.n2;
+    wall |= s->K.wbits != 0;
     pb += s->K.has_outlet ? s->K.plane : 0;
   }
   free_launch(ls);
+  ls.wall = wall;
   ls.ndom = n;
   ls.ntiles = tb;
   ls.nface = fb;
@@ -323,9 +332,12 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
 template <int Q, int ST, int PAR>
 void launch_phi_set(const LaunchSet& ls, hipStream_t st) {
   const dim3 gi(ls.grid), bi(ls.bx * ls.by);
-  if (ls.ntiles)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile, ls.ntiles,
-                       ls.chunk, ls.bx, ls.by);
+  if (ls.ntiles && ls.wall)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+                       ls.ntiles, ls.chunk, ls.bx, ls.by);
+  else if (ls.ntiles)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+                       ls.ntiles, ls.chunk, ls.bx, ls.by);
   if (ls.nface)
     hipLaunchKernelGGL((kb_faces<Q, ST, PAR, false, true>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
                        ls.d_dom, ls.ndom, ls.nface);
@@ -334,9 +346,12 @@ void launch_phi_set(const LaunchSet& ls, hipStream_t st) {
 template <int Q, int ST, int PAR, bool NT>
 void launch_collide_set(const LaunchSet& ls, hipStream_t st) {
   const dim3 gi(ls.grid), bi(ls.bx * ls.by);
-  if (ls.ntiles)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile, ls.ntiles,
-                       ls.chunk, ls.bx, ls.by);
+  if (ls.ntiles && ls.wall)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+                       ls.ntiles, ls.chunk, ls.bx, ls.by);
+  else if (ls.ntiles)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+                       ls.ntiles, ls.chunk, ls.bx, ls.by);
   if (ls.nface)
     hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NT, false>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
                        ls.d_dom, ls.ndom, ls.nface);
@@ -606,6 +621,24 @@ std::map<std::string, TuneEntry> g_tune_cache;
 const int kTiles[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4}, {32, 4}, {16, 16}};
 const int kBpc[] = {2, 4, 8};
 
+// Candidate tiles of the autotuner for boxes whose rows are `w` nodes wide
+// (0: widths differ): the fixed list without mostly idle shapes, plus
+// whole-row tiles (every wave then covers contiguous nodes).
+std::vector<std::pair<int, int>> tile_candidates(int w, int ny) {
+  std::vector<std::pair<int, int>> out;
+  for (const auto& cb : kTiles) {
+    if (w > 0 && cb[0] > 16 && cb[0] >= 2 * w) continue;
+    if (cb[1] > 1 && cb[1] > ny) continue;
+    out.emplace_back(cb[0], cb[1]);
+  }
+  if (w > 0 && w % 16 == 0)
+    for (int by = 1; by <= 8; by *= 2)
+      if (tile_ok(w, by) && by <= ny &&
+          std::find(out.begin(), out.end(), std::make_pair(w, by)) == out.end())
+        out.emplace_back(w, by);
+  return out;
+}
+
 std::string params_key(const lbm_params& p) {
   char buf[200];
   snprintf(buf, sizeof buf, "q%d st%d %dx%dx%d bc%d%d%d%d%d%d", p.lattice, p.storage, p.nx, p.ny, p.nz, p.bc[0],
@@ -752,7 +785,7 @@ int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes) {
 
 int lbm_set_tile(lbm_sim* s, int bx, int by) {
   if (!s) return fail(LBM_EINVAL, "null handle");
-  if (!tile_ok(bx, by)) return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by in {64,128,256,512}");
+  if (!tile_ok(bx, by)) return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by a multiple of 64 up to 512");
   return set_launch(s, bx, by, s->ls.bpc, s->ls.nt);
 }
 
@@ -792,10 +825,8 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
     }
   }
   if (!cached) {
-    for (const auto& cb : kTiles) {
-      const int bx = cb[0], by = cb[1];
-      if (bx > 16 && bx >= 2 * std::max(1, s->box.nx)) continue;  // mostly idle lanes
-      if (by > 1 && by > s->P.ny) continue;
+    for (const auto& cb : tile_candidates(std::max(1, s->box.nx), s->P.ny)) {
+      const int bx = cb.first, by = cb.second;
       for (int bp : kBpc)
         for (int nt = 0; nt < 2; ++nt) {
           int rc = set_launch(s, bx, by, bp, nt);
@@ -1037,18 +1068,20 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blo
     }
   }
   if (!cached) {
-    int minx = 1 << 30;
-    for (auto* v : b->views) minx = std::min(minx, std::max(1, v->box.nx));
-    for (const auto& cb : kTiles) {
-      if (cb[0] > 16 && cb[0] >= 2 * minx) continue;
+    int w = b->views[0]->box.nx, miny = 1 << 30;
+    for (auto* v : b->views) {
+      if (v->box.nx != w) w = 0;
+      miny = std::min(miny, v->P.ny);
+    }
+    for (const auto& cb : tile_candidates(w, miny)) {
       for (int bp : kBpc)
         for (int nt = 0; nt < 2; ++nt) {
-          int rc = batch_set_launch(b, cb[0], cb[1], bp, nt);
+          int rc = batch_set_launch(b, cb.first, cb.second, bp, nt);
           double ms = 0.0;
           if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, 2, &ms);
           if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, trial_steps, &ms);
           if (rc) return rc;
-          if (ms < best.ms) best = {cb[0], cb[1], bp, nt, ms};
+          if (ms < best.ms) best = {cb.first, cb.second, bp, nt, ms};
         }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
