@@ -52,7 +52,7 @@ def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True):
     return sim, dt, kt, mass, ke
 
 
-def run_batch(steps, warmup, storage="fp16", autotune=True):
+def run_batch(steps, warmup, storage="fp16", autotune=True, launch=None):
     """The batched Weber sweep: 64 jet domains 96 x 96 x L_k (seeded lengths
     256..768), We_k log-spaced 0.5..8, one set of launches per step."""
     import torch
@@ -62,7 +62,9 @@ def run_batch(steps, warmup, storage="fp16", autotune=True):
     doms = W.jet_sweep()
     bt = lbm.Batch(doms, storage=storage)
     del doms
-    if autotune:
+    if launch:
+        bt.set_launch(*launch)
+    elif autotune:
         choice = bt.autotune(trial_steps=4)
         print(f"[bench] batch {storage} autotune -> tile {choice[0]}x{choice[1]} blocks/CU={choice[2]} "
               f"nontemporal={choice[3]} {choice[4]:.3f} ms/step", file=sys.stderr, flush=True)
@@ -75,6 +77,27 @@ def run_batch(steps, warmup, storage="fp16", autotune=True):
     kt = bt.kernel_times(6)
     lb = bt.intact_length(0.5)
     return bt.nodes, dt, kt, lb
+
+
+def counted_traffic():
+    """HBM bytes per launch of the fused FP32 step from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
+    of known size), or None when the kernel source has changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        rec = json.load(f)
+    csrc = os.path.join(ROOT, "paper_2505_12205_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("kernels.hpp", "lattice.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+        return None, None
+    return float(rec["traffic_bytes_per_launch"]), rec.get("summary")
 
 
 def copy_probe(gib: float = 2.0, reps: int = 10):
@@ -129,6 +152,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Weber sweep")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
+    ap.add_argument("--blocks-per-cu", type=int, default=8, help="batched launch with --tile")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -144,6 +170,13 @@ def main():
     copy_gbs = copy_probe()
     print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.copy_probe_only:
+        return
+    if args.batch_only:
+        launch = (tile[0], tile[1], args.blocks_per_cu, False) if tile else None
+        nb, dtb, ktb, lb = run_batch(args.steps, args.warmup, "fp16", not args.no_autotune, launch)
+        print(json.dumps({"batched_fp16_MLUPS": round(nb * args.steps / dtb / 1e6, 1), "nodes": nb,
+                          "ms_per_step": round(dtb / args.steps * 1e3, 3), "phi_ms": round(ktb[0], 3),
+                          "step_ms": round(ktb[1], 3), "outlet_ms": round(ktb[2], 4)}), flush=True)
         return
 
     cfg, phi0, u0 = W.rt3d()
@@ -185,6 +218,7 @@ def main():
         print(f"[bench] batched_fp16 {forms['batched_fp16']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
+    traffic, traffic_src = counted_traffic()
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -202,7 +236,9 @@ def main():
                    "storage": "fp32", "atwood": 0.5, "reynolds": 3000, "W": 5,
                    "tile": list(tile_used)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "traffic_source": traffic_src,
+                     "traffic_GBs": round(traffic / (kt[1] * 1e-3) / 1e9, 1) if traffic else None,
                      "kernel": "k_step (fused macroscopic + collisions + AA streaming)",
                      "bytes_per_node": b_k, "kernel_ms": round(kt[1], 4),
                      "phi_pass_ms": round(kt[0], 4), "device_copy_GBs": round(copy_gbs, 1)},

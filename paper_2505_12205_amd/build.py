@@ -1,4 +1,6 @@
-"""Build liblbm.so (the HIP C-ABI library) for gfx950 with hipcc, in-tree."""
+"""Build the HIP C-ABI libraries for gfx950 with hipcc, in-tree:
+liblbm.so (the phase-field LBM step, include/lbm.h) and libsurr.so (the
+learned surrogate's kernels, include/surrogate.h)."""
 from __future__ import annotations
 
 import os
@@ -10,8 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
-SOURCES = ["lbm.hip"]
-HEADERS = ["kernels.hpp", "lattice.hpp"]
+SURR_LIB = os.path.join(LIBDIR, "libsurr.so")
+TARGETS = [(LIB, ["lbm.hip"]), (SURR_LIB, ["nn.hip"])]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
@@ -21,15 +23,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
+def _compile(out: str, sources, verbose: bool):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+           *[os.path.join(CSRC, s) for s in sources], "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
+    return subprocess.Popen(cmd), out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile both libraries (in parallel); returns the LBM library path."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    procs = [_compile(out, srcs, verbose) for out, srcs in TARGETS]
+    failed = [out for p, out in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(failed)})")
+    for _, out in procs:
+        os.replace(out + ".tmp", out)
     return LIB
 
 

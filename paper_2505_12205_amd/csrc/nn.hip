@@ -1,0 +1,770 @@
+// nn.hip -- gfx950 kernels of the learned surrogate (include/surrogate.h).
+//
+// The convolutions are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation):
+//   forward      M = output voxels, N = co, K = 27 taps x ci
+//   data grad    M = input voxels,  N = ci, K = 27 taps x (up^3 sub-positions) x co
+//   weight grad  M = co, N = ci (one tap per block row), K = output voxels
+// Activations are NDHWC bf16 with 16 | C, so one MFMA K-slice is one tap
+// and 16 contiguous channels: every lane reads its 4 operand values with a
+// single 8-byte load.  A wave owns 16*MS voxels x 16*NS channels with
+// MS * NS = 8 accumulator tiles.  The weight gradient stages 64-voxel tiles
+// of dz and of the gathered input in LDS, transposed so that the voxel
+// (reduction) index is contiguous.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "surrogate.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SG_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SG_OK;
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
+  const uint32_t u = __float_as_uint(v);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ v4s ld4(const uint16_t* p) { return *(const v4s*)p; }
+
+__device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+struct Geo {
+  int n, d, h, w;    // layer input extent
+  int ci, co;        // channels
+  int od, oh, ow;    // layer output extent
+  long long mi, mo;  // input / output voxels over the batch
+};
+
+Geo make_geo(int n, int d, int h, int w, int ci, int co, int s, int u) {
+  Geo g;
+  g.n = n;
+  g.d = d;
+  g.h = h;
+  g.w = w;
+  g.ci = ci;
+  g.co = co;
+  g.od = (u * d + s - 1) / s;
+  g.oh = (u * h + s - 1) / s;
+  g.ow = (u * w + s - 1) / s;
+  g.mi = (long long)n * d * h * w;
+  g.mo = (long long)n * g.od * g.oh * g.ow;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// forward: y[v, o] = act(b[o] + sum_{k,c} w[o,k,c] X[src(v,k), c]) (+ skip)
+// ---------------------------------------------------------------------------
+template <int CO, int S, int U>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ wgt,
+                                                  const float* __restrict__ bias,
+                                                  const uint16_t* __restrict__ skip, uint16_t* __restrict__ y,
+                                                  uint16_t* __restrict__ yr, Geo g, int relu) {
+  constexpr int NS = CO / 16;
+  constexpr int MS = 8 / NS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
+  int pz[MS], py[MS], px[MS], nb[MS];
+  bool ok[MS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    long long v = vbase + m * 16 + col;  // A row of this lane
+    ok[m] = v < g.mo;
+    if (!ok[m]) v = 0;
+    px[m] = (int)(v % g.ow);
+    v /= g.ow;
+    py[m] = (int)(v % g.oh);
+    v /= g.oh;
+    pz[m] = (int)(v % g.od);
+    nb[m] = (int)(v / g.od);
+  }
+  v4f acc[MS][NS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const v4s zero = {0, 0, 0, 0};
+  const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
+  for (int kz = 0; kz < 3; ++kz)
+    for (int ky = 0; ky < 3; ++ky)
+      for (int kx = 0; kx < 3; ++kx) {
+        const int tap = (kz * 3 + ky) * 3 + kx;
+        long long src[MS];
+        bool in[MS];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+          const int qz = pz[m] * S + kz - 1, qy = py[m] * S + ky - 1, qx = px[m] * S + kx - 1;
+          in[m] = ok[m] && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+          src[m] = in[m] ? ((((long long)nb[m] * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * g.ci : 0;
+        }
+        const uint16_t* wrow = wgt + (long long)tap * g.ci + 4 * quad;
+        for (int c0 = 0; c0 < g.ci; c0 += 16) {
+          v4s a[MS];
+#pragma unroll
+          for (int m = 0; m < MS; ++m) a[m] = in[m] ? ld4(x + src[m] + c0 + 4 * quad) : zero;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            const v4s b = ld4(wrow + (long long)(s * 16 + col) * 27 * g.ci + c0);
+#pragma unroll
+            for (int m = 0; m < MS; ++m) acc[m][s] = mfma(a[m], b, acc[m][s]);
+          }
+        }
+      }
+  // lane holds D[4 quad + r][col]: voxel row 4 quad + r, channel col
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long v = vbase + m * 16 + 4 * quad + r;
+      if (v >= g.mo) continue;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int o = s * 16 + col;
+        float val = acc[m][s][r] + bias[o];
+        if (relu) val = fmaxf(val, 0.0f);
+        const long long i = v * CO + o;
+        if (yr) yr[i] = f2bf(val);
+        if (skip) val += bf2f(skip[i]);
+        y[i] = f2bf(val);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// data gradient: g[r, c] = sum over (k, p) with src(p, k) = r of w[o,k,c] dz[p, o]
+// ---------------------------------------------------------------------------
+template <int CI, int S, int U>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restrict__ dz,
+                                                       const uint16_t* __restrict__ wt, Geo g,
+                                                       const uint16_t* __restrict__ add,
+                                                       const uint16_t* __restrict__ mask,
+                                                       uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
+  constexpr int NS = CI / 16;
+  constexpr int MS = 8 / NS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
+  int rz[MS], ry[MS], rx[MS], nb[MS];
+  bool ok[MS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    long long v = vbase + m * 16 + col;
+    ok[m] = v < g.mi;
+    if (!ok[m]) v = 0;
+    rx[m] = (int)(v % g.w);
+    v /= g.w;
+    ry[m] = (int)(v % g.h);
+    v /= g.h;
+    rz[m] = (int)(v % g.d);
+    nb[m] = (int)(v / g.d);
+  }
+  v4f acc[MS][NS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const v4s zero = {0, 0, 0, 0};
+  for (int kz = 0; kz < 3; ++kz)
+    for (int ky = 0; ky < 3; ++ky)
+      for (int kx = 0; kx < 3; ++kx) {
+        const int tap = (kz * 3 + ky) * 3 + kx;
+        const uint16_t* wrow = wt + (long long)tap * CI * g.co + 4 * quad;
+        for (int j = 0; j < U * U * U; ++j) {  // sub-position of the upsampled input
+          const int jz = j / (U * U), jy = (j / U) % U, jx = j % U;
+          long long src[MS];
+          bool in[MS];
+#pragma unroll
+          for (int m = 0; m < MS; ++m) {
+            // virtual input position q = r U + j is read by output p when s p + k - 1 = q
+            const int tz = rz[m] * U + jz + 1 - kz, ty = ry[m] * U + jy + 1 - ky, tx = rx[m] * U + jx + 1 - kx;
+            bool v = ok[m] && tz >= 0 && ty >= 0 && tx >= 0;
+            if (S == 2) v = v && !(tz & 1) && !(ty & 1) && !(tx & 1);
+            const int ppz = tz / S, ppy = ty / S, ppx = tx / S;
+            v = v && ppz < g.od && ppy < g.oh && ppx < g.ow;
+            in[m] = v;
+            src[m] = v ? ((((long long)nb[m] * g.od + ppz) * g.oh + ppy) * g.ow + ppx) * g.co : 0;
+          }
+          for (int c0 = 0; c0 < g.co; c0 += 16) {
+            v4s a[MS];
+#pragma unroll
+            for (int m = 0; m < MS; ++m) a[m] = in[m] ? ld4(dz + src[m] + c0 + 4 * quad) : zero;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+              const v4s b = ld4(wrow + (long long)(s * 16 + col) * g.co + c0);
+#pragma unroll
+              for (int m = 0; m < MS; ++m) acc[m][s] = mfma(a[m], b, acc[m][s]);
+            }
+          }
+        }
+      }
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long v = vbase + m * 16 + 4 * quad + r;
+      if (v >= g.mi) continue;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int c = s * 16 + col;
+        const long long i = v * CI + c;
+        float val = acc[m][s][r];
+        if (add) val += bf2f(add[i]);
+        if (da) da[i] = f2bf(val);
+        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
+        dzp[i] = f2bf(val);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient: block (chunk, tap) sums dz[v, o] X[src(v, tap), c] over
+// its voxel chunk; partial[chunk][tap][o][c]; db partials from tap 0 blocks
+// ---------------------------------------------------------------------------
+constexpr int WV = 64;       // voxels per LDS tile
+constexpr int WP = WV + 8;   // padded LDS row (bf16 elements)
+
+// Each wave takes one 16-voxel slice of every 64-voxel tile for all
+// (CO/16) x (CI/16) output tiles; the four waves' sums are added through LDS
+// at the end.  Tap-0 blocks also sum dz (the bias gradient) with an MFMA
+// against a ones operand.
+template <int CO, int CI, int S, int U>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dz,
+                                                    Geo g, long long vchunk, float* __restrict__ part,
+                                                    float* __restrict__ dbpart) {
+  constexpr int NO = CO / 16, NC = CI / 16, NTL = NO * NC;
+  __shared__ __attribute__((aligned(16))) uint16_t dzT[CO * WP];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[CI * WP];
+  __shared__ float red[3 * (NTL + NO) * 256];
+  const int chunk = blockIdx.x, tap = blockIdx.y;
+  const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  const long long v0 = (long long)chunk * vchunk;
+  const long long v1 = v0 + vchunk < g.mo ? v0 + vchunk : g.mo;
+  v4f acc[NTL], accb[NO];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NO; ++t) accb[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const short one = 0x3F80;  // bf16 1.0
+  const v4s ones = {one, one, one, one};
+  const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
+  for (long long vt = v0; vt < v1; vt += WV) {
+    __syncthreads();
+    // dz tile, transposed: dzT[o][voxel]
+    for (int i = threadIdx.x; i < WV * (CO / 4); i += 256) {
+      const int vl = i / (CO / 4), c4 = (i % (CO / 4)) * 4;
+      const long long v = vt + vl;
+      v4s val = {0, 0, 0, 0};
+      if (v < v1) val = ld4(dz + v * CO + c4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dzT[(c4 + j) * WP + vl] = (uint16_t)val[j];
+    }
+    // gathered input of this tap, transposed: xT[c][voxel]
+    for (int i = threadIdx.x; i < WV * (CI / 4); i += 256) {
+      const int vl = i / (CI / 4), c4 = (i % (CI / 4)) * 4;
+      long long v = vt + vl;
+      v4s val = {0, 0, 0, 0};
+      if (v < v1) {
+        const int px = (int)(v % g.ow);
+        v /= g.ow;
+        const int py = (int)(v % g.oh);
+        v /= g.oh;
+        const int pz = (int)(v % g.od);
+        const int n = (int)(v / g.od);
+        const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
+        if (qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU)
+          val = ld4(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * CI + c4);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xT[(c4 + j) * WP + vl] = (uint16_t)val[j];
+    }
+    __syncthreads();
+    const int kofs = wv * 16 + 4 * quad;  // this wave's voxel slice
+    v4s a[NO], b[NC];
+#pragma unroll
+    for (int t = 0; t < NO; ++t) a[t] = *(const v4s*)&dzT[(t * 16 + col) * WP + kofs];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) b[t] = *(const v4s*)&xT[(t * 16 + col) * WP + kofs];
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct) acc[ot * NC + ct] = mfma(a[ot], b[ct], acc[ot * NC + ct]);
+    if (tap == 0)
+#pragma unroll
+      for (int ot = 0; ot < NO; ++ot) accb[ot] = mfma(a[ot], ones, accb[ot]);
+  }
+  // add the four waves' sums: waves 1..3 park theirs in LDS
+  if (wv > 0) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((wv - 1) * (NTL + NO) + t) * 256 + r * 64 + lane] = acc[t][r];
+#pragma unroll
+    for (int t = 0; t < NO; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((wv - 1) * (NTL + NO) + NTL + t) * 256 + r * 64 + lane] = accb[t][r];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[t][r] += red[(k * (NTL + NO) + t) * 256 + r * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < NO; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accb[t][r] += red[(k * (NTL + NO) + NTL + t) * 256 + r * 64 + lane];
+  }
+  // lane holds D[4 quad + r][col]: o = ot*16 + 4 quad + r, c = ct*16 + col
+#pragma unroll
+  for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+    for (int ct = 0; ct < NC; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = ot * 16 + 4 * quad + r, c = ct * 16 + col;
+        part[(((long long)chunk * 27 + tap) * CO + o) * CI + c] = acc[ot * NC + ct][r];
+      }
+  if (tap == 0 && col == 0)  // every column of the ones product holds the row sum
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dbpart[(long long)chunk * CO + ot * 16 + 4 * quad + r] = accb[ot][r];
+}
+
+__global__ void k_bwd_w_reduce(const float* __restrict__ part, const float* __restrict__ dbpart, int nchunk, int co,
+                               int ci, float* __restrict__ dw, float* __restrict__ db) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [tap][o][c]
+  const int n = 27 * co * ci;
+  if (i < n) {
+    float s = 0.0f;
+    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * n + i];
+    const int c = i % ci, o = (i / ci) % co, tap = i / (ci * co);
+    dw[((long long)o * 27 + tap) * ci + c] = s;
+  }
+  if (i < co) {
+    float s = 0.0f;
+    for (int k = 0; k < nchunk; ++k) s += dbpart[(long long)k * co + i];
+    db[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_transpose_w(const uint16_t* __restrict__ w, int co, int ci, uint16_t* __restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [o][k][c]
+  if (i >= co * 27 * ci) return;
+  const int c = i % ci, k = (i / ci) % 27, o = i / (ci * 27);
+  wt[((long long)k * ci + c) * co + o] = w[i];
+}
+
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, long long count, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, uint16_t* __restrict__ pb) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  p[i] = pi;
+  if (pb) pb[i] = f2bf(pi);
+}
+
+__global__ void k_normalize(const float* __restrict__ x, int c, long long vox, long long total,
+                            const float* __restrict__ shift, const float* __restrict__ scale, float* xn) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int ch = (int)((i / vox) % c);
+  xn[i] = (x[i] - shift[ch]) * scale[ch];
+}
+
+__global__ void k_pack(const float* __restrict__ xn, int c, long long vox, int cpad, long long total,
+                       uint16_t* __restrict__ xb) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][vox][cpad]
+  if (i >= total) return;
+  const int ch = (int)(i % cpad);
+  const long long v = (i / cpad) % vox, n = i / (cpad * vox);
+  xb[i] = ch < c ? f2bf(xn[(n * c + ch) * vox + v]) : (uint16_t)0;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+  __syncthreads();
+  return s;
+}
+
+constexpr int kLossBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__ xn, const float* __restrict__ tn,
+                                                       const uint16_t* __restrict__ r, int c, long long vox,
+                                                       int cpad, long long total, float inv_count,
+                                                       uint16_t* __restrict__ dr, double* __restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {  // over [n][vox][cpad]
+    const int ch = (int)(i % cpad);
+    float gval = 0.0f;
+    if (ch < c) {
+      const long long v = (i / cpad) % vox, n = i / (cpad * vox);
+      const long long j = (n * c + ch) * vox + v;
+      const float d = xn[j] + bf2f(r[i]) - tn[j];
+      s += (double)d * d;
+      gval = 2.0f * d * inv_count;
+    }
+    dr[i] = f2bf(gval);
+  }
+  const double b = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+  }
+}
+
+__global__ void k_unpack(const float* __restrict__ xn, const uint16_t* __restrict__ r, int c, long long vox,
+                         int cpad, long long total, const float* __restrict__ shift,
+                         const float* __restrict__ scale, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][c][vox]
+  if (i >= total) return;
+  const long long v = i % vox;
+  const int ch = (int)((i / vox) % c);
+  const long long n = i / (vox * c);
+  out[i] = (xn[i] + bf2f(r[(n * vox + v) * cpad + ch])) / scale[ch] + shift[ch];
+}
+
+__global__ void k_coarsen(const float* __restrict__ phi, const float* __restrict__ u, const float* __restrict__ p,
+                          int nx, int ny, int nz, int z0c, int dw, float* __restrict__ out) {
+  const int hx = nx / 2, hy = ny / 2;
+  const long long plane = (long long)hx * hy, vol = plane * dw;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [5][dw][hy][hx]
+  if (i >= 5 * vol) return;
+  const int ch = (int)(i / vol);
+  const long long r = i % vol;
+  const int zc = (int)(r / plane) + z0c, yc = (int)((r % plane) / hx), xc = (int)(r % hx);
+  float s = 0.0f;
+  if (2 * zc + 1 < nz) {
+    const long long N = (long long)nx * ny * nz;
+    const float* f = ch == 0 ? phi : (ch == 4 ? p : u + (long long)(ch - 1) * N);
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+          s += f[((long long)(2 * zc + dz) * ny + (2 * yc + dy)) * nx + (2 * xc + dx)];
+    s *= 0.125f;
+  }
+  out[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_phi_budget(const float* __restrict__ x, int c, int d, int h, int w,
+                                                    double* __restrict__ sums) {
+  __shared__ double sh[4];
+  const int n = blockIdx.x;
+  const long long plane = (long long)h * w, vox = plane * d;
+  const float* phi = x + (long long)n * c * vox;
+  const float* uz = phi + 3 * vox;
+  double s = 0.0, fi = 0.0, fo = 0.0;
+  for (long long i = threadIdx.x; i < vox; i += blockDim.x) s += phi[i];
+  for (long long i = threadIdx.x; i < plane; i += blockDim.x) {
+    fi += (double)phi[i] * uz[i];
+    fo += (double)phi[(d - 1) * plane + i] * uz[(d - 1) * plane + i];
+  }
+  const double a = block_sum(s, sh);
+  const double b = block_sum(fi, sh);
+  const double e = block_sum(fo, sh);
+  if (threadIdx.x == 0) {
+    sums[3 * n + 0] = a;
+    sums[3 * n + 1] = b;
+    sums[3 * n + 2] = e;
+  }
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, long long count, uint16_t* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = f2bf(x[i]);
+}
+
+__global__ void k_gather(const uint16_t* __restrict__ store, long long rows, long long len,
+                         const long long* __restrict__ idx, int n, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][len]
+  if (i >= (long long)n * len) return;
+  const long long j = i / len, e = i % len;
+  const long long r = idx[j];
+  out[i] = (r >= 0 && r < rows) ? bf2f(store[r * len + e]) : __int_as_float(0x7fc00000);
+}
+
+bool chan_ok(int c) { return c == 16 || c == 32 || c == 64; }
+
+unsigned blocks_for(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int CO, int S, int U>
+void launch_fwd(const Geo& g, const uint16_t* x, const uint16_t* w, const float* b, const uint16_t* skip,
+                uint16_t* y, uint16_t* yr, int relu, hipStream_t st) {
+  constexpr int MS = 8 / (CO / 16);
+  const long long per_block = 4LL * 16 * MS;
+  hipLaunchKernelGGL((k_conv_fwd<CO, S, U>), dim3(blocks_for(g.mo, (int)per_block)), dim3(256), 0, st, x, w, b,
+                     skip, y, yr, g, relu);
+}
+
+template <int S, int U>
+void launch_fwd_su(const Geo& g, const uint16_t* x, const uint16_t* w, const float* b, const uint16_t* skip,
+                   uint16_t* y, uint16_t* yr, int relu, hipStream_t st) {
+  if (g.co == 16) launch_fwd<16, S, U>(g, x, w, b, skip, y, yr, relu, st);
+  else if (g.co == 32) launch_fwd<32, S, U>(g, x, w, b, skip, y, yr, relu, st);
+  else launch_fwd<64, S, U>(g, x, w, b, skip, y, yr, relu, st);
+}
+
+template <int CI, int S, int U>
+void launch_bwd_data(const Geo& g, const uint16_t* dz, const uint16_t* wt, const uint16_t* add,
+                     const uint16_t* mask, uint16_t* da, uint16_t* dzp, hipStream_t st) {
+  constexpr int MS = 8 / (CI / 16);
+  const long long per_block = 4LL * 16 * MS;
+  hipLaunchKernelGGL((k_conv_bwd_data<CI, S, U>), dim3(blocks_for(g.mi, (int)per_block)), dim3(256), 0, st, dz,
+                     wt, g, add, mask, da, dzp);
+}
+
+template <int S, int U>
+void launch_bwd_data_su(const Geo& g, const uint16_t* dz, const uint16_t* wt, const uint16_t* add,
+                        const uint16_t* mask, uint16_t* da, uint16_t* dzp, hipStream_t st) {
+  if (g.ci == 16) launch_bwd_data<16, S, U>(g, dz, wt, add, mask, da, dzp, st);
+  else if (g.ci == 32) launch_bwd_data<32, S, U>(g, dz, wt, add, mask, da, dzp, st);
+  else launch_bwd_data<64, S, U>(g, dz, wt, add, mask, da, dzp, st);
+}
+
+template <int CO, int S, int U>
+void launch_bwd_w_co(const Geo& g, const uint16_t* x, const uint16_t* dz, int nchunk, long long vchunk,
+                     float* part, float* dbpart, hipStream_t st) {
+  const dim3 grid(nchunk, 27);
+  if (g.ci == 16)
+    hipLaunchKernelGGL((k_conv_bwd_w<CO, 16, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
+  else if (g.ci == 32)
+    hipLaunchKernelGGL((k_conv_bwd_w<CO, 32, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
+  else
+    hipLaunchKernelGGL((k_conv_bwd_w<CO, 64, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
+}
+
+template <int S, int U>
+void launch_bwd_w_su(const Geo& g, const uint16_t* x, const uint16_t* dz, int nchunk, long long vchunk,
+                     float* part, float* dbpart, hipStream_t st) {
+  if (g.co == 16) launch_bwd_w_co<16, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else if (g.co == 32) launch_bwd_w_co<32, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else launch_bwd_w_co<64, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+}
+
+// voxel chunking of the weight gradient: about 2048 blocks over the 27 taps
+void wchunks(const Geo& g, int& nchunk, long long& vchunk) {
+  const long long target = 76;
+  long long vc = (g.mo + target - 1) / target;
+  vc = ((vc + WV - 1) / WV) * WV;
+  if (vc < WV) vc = WV;
+  vchunk = vc;
+  nchunk = (int)((g.mo + vc - 1) / vc);
+  if (nchunk < 1) nchunk = 1;
+}
+
+int check_conv(int n, int d, int h, int w, int ci, int co, int stride, int up) {
+  if (n < 1 || d < 1 || h < 1 || w < 1) return fail(SG_EINVAL, "empty extent");
+  if (!chan_ok(ci) || !chan_ok(co)) return fail(SG_EINVAL, "channels must be 16, 32 or 64");
+  if (!((stride == 1 || stride == 2) && (up == 1 || up == 2)) || (stride == 2 && up == 2))
+    return fail(SG_EINVAL, "stride/upsample must be (1,1), (2,1) or (1,2)");
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+
+int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* wgt, const float* bias,
+                  int co, int stride, int up, int relu, const uint16_t* skip, uint16_t* y, uint16_t* yr,
+                  void* stream) {
+  int rc = check_conv(n, d, h, w, ci, co, stride, up);
+  if (rc) return rc;
+  if (!x || !wgt || !bias || !y) return fail(SG_EINVAL, "null tensor");
+  const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
+  hipStream_t st = (hipStream_t)stream;
+  if (stride == 1 && up == 1) launch_fwd_su<1, 1>(g, x, wgt, bias, skip, y, yr, relu, st);
+  else if (stride == 2) launch_fwd_su<2, 1>(g, x, wgt, bias, skip, y, yr, relu, st);
+  else launch_fwd_su<1, 2>(g, x, wgt, bias, skip, y, yr, relu, st);
+  return check_launch("sg_conv3d_fwd");
+}
+
+int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wgt_t, int co,
+                       int stride, int up, const uint16_t* add, const uint16_t* mask, uint16_t* da, uint16_t* dzp,
+                       void* stream) {
+  int rc = check_conv(n, d, h, w, ci, co, stride, up);
+  if (rc) return rc;
+  if (!dz || !wgt_t || !dzp) return fail(SG_EINVAL, "null tensor");
+  const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
+  hipStream_t st = (hipStream_t)stream;
+  if (stride == 1 && up == 1) launch_bwd_data_su<1, 1>(g, dz, wgt_t, add, mask, da, dzp, st);
+  else if (stride == 2) launch_bwd_data_su<2, 1>(g, dz, wgt_t, add, mask, da, dzp, st);
+  else launch_bwd_data_su<1, 2>(g, dz, wgt_t, add, mask, da, dzp, st);
+  return check_launch("sg_conv3d_bwd_data");
+}
+
+size_t sg_conv3d_bwd_weight_workspace(int n, int d, int h, int w, int ci, int co, int stride, int up) {
+  if (check_conv(n, d, h, w, ci, co, stride, up)) return 0;
+  const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
+  int nchunk;
+  long long vchunk;
+  wchunks(g, nchunk, vchunk);
+  return (size_t)nchunk * (27 * (size_t)co * ci + co) * sizeof(float);
+}
+
+int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* dz, int co,
+                         int stride, int up, void* ws, size_t ws_bytes, float* dw, float* db, void* stream) {
+  int rc = check_conv(n, d, h, w, ci, co, stride, up);
+  if (rc) return rc;
+  if (!x || !dz || !ws || !dw || !db) return fail(SG_EINVAL, "null tensor");
+  if (ws_bytes < sg_conv3d_bwd_weight_workspace(n, d, h, w, ci, co, stride, up))
+    return fail(SG_EINVAL, "workspace too small");
+  const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
+  int nchunk;
+  long long vchunk;
+  wchunks(g, nchunk, vchunk);
+  float* part = (float*)ws;
+  float* dbpart = part + (size_t)nchunk * 27 * co * ci;
+  hipStream_t st = (hipStream_t)stream;
+  if (stride == 1 && up == 1) launch_bwd_w_su<1, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else if (stride == 2) launch_bwd_w_su<2, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else launch_bwd_w_su<1, 2>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  const int nred = 27 * co * ci;
+  hipLaunchKernelGGL(k_bwd_w_reduce, dim3(blocks_for(nred, 256)), dim3(256), 0, st, part, dbpart, nchunk, co, ci,
+                     dw, db);
+  return check_launch("sg_conv3d_bwd_weight");
+}
+
+int sg_transpose_weights(const uint16_t* w, int co, int ci, uint16_t* wt, void* stream) {
+  if (!w || !wt || !chan_ok(co) || !chan_ok(ci)) return fail(SG_EINVAL, "bad weights");
+  const int n = co * 27 * ci;
+  hipLaunchKernelGGL(k_transpose_w, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, co, ci, wt);
+  return check_launch("sg_transpose_weights");
+}
+
+int sg_adam(float* p, float* m, float* v, const float* g, long long count, int t, float lr, float beta1,
+            float beta2, float eps, uint16_t* pb, void* stream) {
+  if (!p || !m || !v || !g || count < 0 || t < 1) return fail(SG_EINVAL, "bad optimiser arguments");
+  if (count == 0) return SG_OK;
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, t));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, t));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, p, m, v, g, count,
+                     lr, beta1, beta2, eps, bc1, bc2, pb);
+  return check_launch("sg_adam");
+}
+
+int sg_normalize(const float* x, int n, int c, long long vox, const float* shift, const float* scale, float* xn,
+                 void* stream) {
+  if (!x || !shift || !scale || !xn || n < 1 || c < 1 || vox < 1) return fail(SG_EINVAL, "bad normalize");
+  const long long total = (long long)n * c * vox;
+  hipLaunchKernelGGL(k_normalize, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, x, c, vox,
+                     total, shift, scale, xn);
+  return check_launch("sg_normalize");
+}
+
+int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb, void* stream) {
+  if (!xn || !xb || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c) return fail(SG_EINVAL, "bad pack");
+  const long long total = (long long)n * vox * cpad;
+  hipLaunchKernelGGL(k_pack, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, xn, c, vox, cpad,
+                     total, xb);
+  return check_launch("sg_pack");
+}
+
+int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, int n, int c, long long vox, int cpad,
+                     uint16_t* dr, double* loss, void* ws, void* stream) {
+  if (!xn || !tn || !r || !dr || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
+    return fail(SG_EINVAL, "bad loss arguments");
+  if (loss && !ws) return fail(SG_EINVAL, "loss needs a workspace");
+  const long long total = (long long)n * vox * cpad;
+  const double count = (double)n * c * vox;
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)ws;
+  if (!part) return fail(SG_EINVAL, "loss needs a workspace");
+  hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, c, vox, cpad, total,
+                     (float)(1.0 / count), dr, part);
+  if (loss) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kLossBlocks, 1.0 / count, loss);
+  return check_launch("sg_residual_loss");
+}
+
+int sg_unpack(const float* xn, const uint16_t* r, int n, int c, long long vox, int cpad, const float* shift,
+              const float* scale, float* out, void* stream) {
+  if (!xn || !r || !shift || !scale || !out || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
+    return fail(SG_EINVAL, "bad unpack");
+  const long long total = (long long)n * c * vox;
+  hipLaunchKernelGGL(k_unpack, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, xn, r, c, vox,
+                     cpad, total, shift, scale, out);
+  return check_launch("sg_unpack");
+}
+
+int sg_coarsen(const float* phi, const float* u, const float* p, int nx, int ny, int nz, int z0c, int dw,
+               float* out, void* stream) {
+  if (!phi || !u || !p || !out || nx < 2 || ny < 2 || nz < 2 || (nx & 1) || (ny & 1) || z0c < 0 || dw < 1)
+    return fail(SG_EINVAL, "bad coarsen");
+  const long long total = 5LL * dw * (nx / 2) * (ny / 2);
+  hipLaunchKernelGGL(k_coarsen, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, phi, u, p, nx, ny,
+                     nz, z0c, dw, out);
+  return check_launch("sg_coarsen");
+}
+
+int sg_phi_budget(const float* x, int n, int c, int d, int h, int w, double* sums, void* stream) {
+  if (!x || !sums || n < 1 || c < 4 || d < 1 || h < 1 || w < 1) return fail(SG_EINVAL, "bad budget");
+  hipLaunchKernelGGL(k_phi_budget, dim3(n), dim3(256), 0, (hipStream_t)stream, x, c, d, h, w, sums);
+  return check_launch("sg_phi_budget");
+}
+
+int sg_cast_bf16(const float* x, long long count, uint16_t* y, void* stream) {
+  if (!x || !y || count < 0) return fail(SG_EINVAL, "bad cast");
+  if (count == 0) return SG_OK;
+  hipLaunchKernelGGL(k_cast_bf16, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, x, count, y);
+  return check_launch("sg_cast_bf16");
+}
+
+int sg_gather(const uint16_t* store, long long rows, long long len, const long long* idx, int n, float* out,
+              void* stream) {
+  if (!store || !idx || !out || rows < 1 || len < 1 || n < 0) return fail(SG_EINVAL, "bad gather");
+  if (n == 0) return SG_OK;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for((long long)n * len, 256)), dim3(256), 0, (hipStream_t)stream,
+                     store, rows, len, idx, n, out);
+  return check_launch("sg_gather");
+}
+
+}  // extern "C"

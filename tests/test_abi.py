@@ -62,3 +62,27 @@ def test_invalid_parameters_rejected_on_host(bad, code):
     with pytest.raises(lbm.LbmError) as ei:
         lbm.state_bytes(_cfg(**bad))
     assert ei.value.code == code
+
+
+def _declared_surrogate():
+    txt = open(os.path.join(ROOT, "include", "surrogate.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_surrogate_library_exports_every_declared_symbol():
+    from paper_2505_12205_amd import nn
+    names = _declared_surrogate()
+    assert "sg_conv3d_fwd" in names and "sg_conv3d_bwd_weight" in names
+    for n in names:
+        assert hasattr(nn.lib, n), n
+    assert set(names) == set(nn.EXPORTED)
+
+
+def test_surrogate_rejects_bad_sizes_on_host():
+    from paper_2505_12205_amd import nn
+    # channels must be 16, 32 or 64; stride 2 with upsampling is not a form
+    assert nn.lib.sg_conv3d_fwd(None, 1, 4, 4, 4, 8, None, None, 16, 1, 1, 1, None, None, None, None) == -1
+    assert nn.lib.sg_conv3d_fwd(None, 1, 4, 4, 4, 16, None, None, 16, 2, 2, 1, None, None, None, None) == -1
+    assert nn.lib.sg_conv3d_bwd_weight_workspace(1, 4, 4, 4, 16, 16, 2, 2) == 0
+    assert nn.lib.sg_conv3d_bwd_weight_workspace(2, 8, 8, 8, 16, 32, 2, 1) > 0
