@@ -89,17 +89,19 @@ int sg_normalize(const float* x, int n, int c, long long vox, const float* shift
  * c..cpad-1 zero), cpad a multiple of 16 >= c. */
 int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb, void* stream);
 
-/* Residual loss: pred = xn + r[..., c], L = mean over n c vox of (pred - tn)^2.
+/* Residual loss: pred = xn + rs[c] r[..., c] (rs: device array of c
+ * increment scales, null for ones), L = mean over n c vox of (pred - tn)^2.
  * r [n, vox, cpad] bf16 (the last layer's output); writes dr [n, vox, cpad]
  * = dL/dr (zero in the padding channels) and, if loss is non-null, L as a
  * double.  ws (required): device workspace of 1024 doubles for the FP64
  * partial sums, added in a fixed order. */
-int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, int n, int c, long long vox,
-                     int cpad, uint16_t* dr, double* loss, void* ws, void* stream);
+int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, const float* rs, int n, int c,
+                     long long vox, int cpad, uint16_t* dr, double* loss, void* ws, void* stream);
 
-/* Prediction in physical units: out[n, c, vox] = (xn + r[..., c]) / scale[c] + shift[c]. */
-int sg_unpack(const float* xn, const uint16_t* r, int n, int c, long long vox, int cpad, const float* shift,
-              const float* scale, float* out, void* stream);
+/* Prediction in physical units:
+ * out[n, c, vox] = (xn + rs[c] r[..., c]) / scale[c] + shift[c] (rs nullable). */
+int sg_unpack(const float* xn, const uint16_t* r, const float* rs, int n, int c, long long vox, int cpad,
+              const float* shift, const float* scale, float* out, void* stream);
 
 /* Coarse window of solver fields: phi [nz, ny, nx], u [3][nz][ny][nx],
  * p [nz, ny, nx] (the layout of lbm_fields) averaged over
@@ -115,14 +117,11 @@ int sg_coarsen(const float* phi, const float* u, const float* p, int nx, int ny,
  * same over z = d - 1.  sums is a device array of 3 n doubles. */
 int sg_phi_budget(const float* x, int n, int c, int d, int h, int w, double* sums, void* stream);
 
-/* bf16 copy of a float array (round to nearest even): y[i] = bf16(x[i]). */
-int sg_cast_bf16(const float* x, long long count, uint16_t* y, void* stream);
-
-/* Gather rows of a bf16 store into float: out[j, :] = store[idx[j], :] for
- * j < n, rows of `len` elements; idx is a device array of n row indices,
- * each in [0, rows) (checked on the device: an index out of range yields a
- * row of NaN). */
-int sg_gather(const uint16_t* store, long long rows, long long len, const long long* idx, int n, float* out,
+/* Gather rows of a float store: out[j, :] = store[idx[j], :] for j < n,
+ * rows of `len` elements; idx is a device array of n row indices, each in
+ * [0, rows) (checked on the device: an index out of range yields a row of
+ * NaN). */
+int sg_gather(const float* store, long long rows, long long len, const long long* idx, int n, float* out,
               void* stream);
 
 #ifdef __cplusplus

@@ -15,7 +15,8 @@ optimiser are this project's own definitions, written out plainly here:
       y[n, o, p] = b[o] + sum_{c, k} w[o, c, k] * X[n, c, s p + k - 1],
   X the (upsampled, u = 2: X[q] = x[q // 2]) input, zero outside its extent.
 * relu(z) = max(z, 0); skip connections add a stored activation after the
-  relu; the output is the input plus the last (linear) layer: x + r(x).
+  relu; the output is the input plus the last (linear) layer times a fixed
+  increment scale: x + scale r(x).
 * loss = mean over all elements of (prediction - target)^2.
 * Adam with bias correction (Kingma & Ba, Algorithm 1).
 
@@ -157,9 +158,9 @@ def conv3d_direct(x, w, b, s=1, u=1):
 # network forward / backward, loss, optimiser
 # ---------------------------------------------------------------------------
 
-def forward(P, spec, x):
-    """Returns (prediction, cache).  cache[name] = (input, pre-activation,
-    post-activation incl. skip)."""
+def forward(P, spec, x, scale=1.0):
+    """Returns (prediction x + scale r(x), cache).  cache[name] = (input,
+    pre-activation)."""
     cache = {}
     h = x
     out = {}
@@ -171,7 +172,7 @@ def forward(P, spec, x):
         cache[name] = (h, z)
         out[name] = a
         h = a
-    return x + h, cache
+    return x + scale * h, cache
 
 
 def mse(pred, target):
@@ -179,11 +180,11 @@ def mse(pred, target):
     return float(np.mean(d * d)), 2.0 * d / d.size
 
 
-def backward(P, spec, cache, dpred):
+def backward(P, spec, cache, dpred, scale=1.0):
     """Gradients of the loss given dL/dprediction."""
     G = {}
     dout = {name: None for (name, *_rest) in spec}
-    dh = dpred.copy()  # into the last layer's output (the residual branch)
+    dh = scale * dpred  # into the last layer's output (the scaled residual branch)
     for (name, ci, co, s, u, relu, skip) in reversed(spec):
         da = dh if dout[name] is None else dh + dout[name]
         if skip is not None:  # a = relu(z) + out[skip]
@@ -197,10 +198,10 @@ def backward(P, spec, cache, dpred):
     return G, dh + dpred  # d/dx includes the identity path
 
 
-def loss_and_grad(P, spec, x, target):
-    pred, cache = forward(P, spec, x)
+def loss_and_grad(P, spec, x, target, scale=1.0):
+    pred, cache = forward(P, spec, x, scale)
     L, dpred = mse(pred, target)
-    G, _ = backward(P, spec, cache, dpred)
+    G, _ = backward(P, spec, cache, dpred, scale)
     return L, G
 
 

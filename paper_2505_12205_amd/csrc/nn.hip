@@ -431,7 +431,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 constexpr int kLossBlocks = 1024;
 
 __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__ xn, const float* __restrict__ tn,
-                                                       const uint16_t* __restrict__ r, int c, long long vox,
+                                                       const uint16_t* __restrict__ r,
+                                                       const float* __restrict__ rs, int c, long long vox,
                                                        int cpad, long long total, float inv_count,
                                                        uint16_t* __restrict__ dr, double* __restrict__ part) {
   __shared__ double sh[4];
@@ -443,9 +444,10 @@ __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__
     if (ch < c) {
       const long long v = (i / cpad) % vox, n = i / (cpad * vox);
       const long long j = (n * c + ch) * vox + v;
-      const float d = xn[j] + bf2f(r[i]) - tn[j];
+      const float sc = rs ? rs[ch] : 1.0f;
+      const float d = xn[j] + sc * bf2f(r[i]) - tn[j];
       s += (double)d * d;
-      gval = 2.0f * d * inv_count;
+      gval = 2.0f * sc * d * inv_count;
     }
     dr[i] = f2bf(gval);
   }
@@ -461,15 +463,16 @@ __global__ void k_sum_parts(const double* __restrict__ part, int n, double scale
   }
 }
 
-__global__ void k_unpack(const float* __restrict__ xn, const uint16_t* __restrict__ r, int c, long long vox,
-                         int cpad, long long total, const float* __restrict__ shift,
+__global__ void k_unpack(const float* __restrict__ xn, const uint16_t* __restrict__ r, const float* __restrict__ rs,
+                         int c, long long vox, int cpad, long long total, const float* __restrict__ shift,
                          const float* __restrict__ scale, float* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][c][vox]
   if (i >= total) return;
   const long long v = i % vox;
   const int ch = (int)((i / vox) % c);
   const long long n = i / (vox * c);
-  out[i] = (xn[i] + bf2f(r[(n * vox + v) * cpad + ch])) / scale[ch] + shift[ch];
+  const float sc = rs ? rs[ch] : 1.0f;
+  out[i] = (xn[i] + sc * bf2f(r[(n * vox + v) * cpad + ch])) / scale[ch] + shift[ch];
 }
 
 __global__ void k_coarsen(const float* __restrict__ phi, const float* __restrict__ u, const float* __restrict__ p,
@@ -517,18 +520,13 @@ __global__ __launch_bounds__(256) void k_phi_budget(const float* __restrict__ x,
   }
 }
 
-__global__ void k_cast_bf16(const float* __restrict__ x, long long count, uint16_t* __restrict__ y) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) y[i] = f2bf(x[i]);
-}
-
-__global__ void k_gather(const uint16_t* __restrict__ store, long long rows, long long len,
+__global__ void k_gather(const float* __restrict__ store, long long rows, long long len,
                          const long long* __restrict__ idx, int n, float* __restrict__ out) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][len]
   if (i >= (long long)n * len) return;
   const long long j = i / len, e = i % len;
   const long long r = idx[j];
-  out[i] = (r >= 0 && r < rows) ? bf2f(store[r * len + e]) : __int_as_float(0x7fc00000);
+  out[i] = (r >= 0 && r < rows) ? store[r * len + e] : __int_as_float(0x7fc00000);
 }
 
 bool chan_ok(int c) { return c == 16 || c == 32 || c == 64; }
@@ -709,28 +707,26 @@ int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb
   return check_launch("sg_pack");
 }
 
-int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, int n, int c, long long vox, int cpad,
-                     uint16_t* dr, double* loss, void* ws, void* stream) {
-  if (!xn || !tn || !r || !dr || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
+int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, const float* rs, int n, int c,
+                     long long vox, int cpad, uint16_t* dr, double* loss, void* ws, void* stream) {
+  if (!xn || !tn || !r || !dr || !ws || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
     return fail(SG_EINVAL, "bad loss arguments");
-  if (loss && !ws) return fail(SG_EINVAL, "loss needs a workspace");
   const long long total = (long long)n * vox * cpad;
   const double count = (double)n * c * vox;
   hipStream_t st = (hipStream_t)stream;
   double* part = (double*)ws;
-  if (!part) return fail(SG_EINVAL, "loss needs a workspace");
-  hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, c, vox, cpad, total,
+  hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, total,
                      (float)(1.0 / count), dr, part);
   if (loss) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kLossBlocks, 1.0 / count, loss);
   return check_launch("sg_residual_loss");
 }
 
-int sg_unpack(const float* xn, const uint16_t* r, int n, int c, long long vox, int cpad, const float* shift,
-              const float* scale, float* out, void* stream) {
+int sg_unpack(const float* xn, const uint16_t* r, const float* rs, int n, int c, long long vox, int cpad,
+              const float* shift, const float* scale, float* out, void* stream) {
   if (!xn || !r || !shift || !scale || !out || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
     return fail(SG_EINVAL, "bad unpack");
   const long long total = (long long)n * c * vox;
-  hipLaunchKernelGGL(k_unpack, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, xn, r, c, vox,
+  hipLaunchKernelGGL(k_unpack, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, xn, r, rs, c, vox,
                      cpad, total, shift, scale, out);
   return check_launch("sg_unpack");
 }
@@ -751,14 +747,7 @@ int sg_phi_budget(const float* x, int n, int c, int d, int h, int w, double* sum
   return check_launch("sg_phi_budget");
 }
 
-int sg_cast_bf16(const float* x, long long count, uint16_t* y, void* stream) {
-  if (!x || !y || count < 0) return fail(SG_EINVAL, "bad cast");
-  if (count == 0) return SG_OK;
-  hipLaunchKernelGGL(k_cast_bf16, dim3(blocks_for(count, 256)), dim3(256), 0, (hipStream_t)stream, x, count, y);
-  return check_launch("sg_cast_bf16");
-}
-
-int sg_gather(const uint16_t* store, long long rows, long long len, const long long* idx, int n, float* out,
+int sg_gather(const float* store, long long rows, long long len, const long long* idx, int n, float* out,
               void* stream) {
   if (!store || !idx || !out || rows < 1 || len < 1 || n < 0) return fail(SG_EINVAL, "bad gather");
   if (n == 0) return SG_OK;

@@ -40,11 +40,10 @@ def _load():
     L.sg_adam.argtypes = [vp, vp, vp, vp, ll, i, f, f, f, f, vp, vp]
     L.sg_normalize.argtypes = [vp, i, i, ll, vp, vp, vp, vp]
     L.sg_pack.argtypes = [vp, i, i, ll, i, vp, vp]
-    L.sg_residual_loss.argtypes = [vp, vp, vp, i, i, ll, i, vp, vp, vp, vp]
-    L.sg_unpack.argtypes = [vp, vp, i, i, ll, i, vp, vp, vp, vp]
+    L.sg_residual_loss.argtypes = [vp, vp, vp, vp, i, i, ll, i, vp, vp, vp, vp]
+    L.sg_unpack.argtypes = [vp, vp, vp, i, i, ll, i, vp, vp, vp, vp]
     L.sg_coarsen.argtypes = [vp, vp, vp, i, i, i, i, i, vp, vp]
     L.sg_phi_budget.argtypes = [vp, i, i, i, i, i, vp, vp]
-    L.sg_cast_bf16.argtypes = [vp, ll, vp, vp]
     L.sg_gather.argtypes = [vp, ll, ll, vp, i, vp, vp]
     return L
 
@@ -53,7 +52,7 @@ lib = _load()
 
 EXPORTED = ("sg_last_error", "sg_conv3d_fwd", "sg_conv3d_bwd_data", "sg_conv3d_bwd_weight_workspace",
             "sg_conv3d_bwd_weight", "sg_transpose_weights", "sg_adam", "sg_normalize", "sg_pack",
-            "sg_residual_loss", "sg_unpack", "sg_coarsen", "sg_phi_budget", "sg_cast_bf16", "sg_gather")
+            "sg_residual_loss", "sg_unpack", "sg_coarsen", "sg_phi_budget", "sg_gather")
 
 
 def _check(rc):
@@ -134,18 +133,21 @@ def pack(xn, cpad, out=None, stream=None):
     return out
 
 
-def residual_loss(xn, tn, r, dr, loss=None, ws=None, stream=None):
+def residual_loss(xn, tn, r, dr, loss=None, ws=None, rs=None, stream=None):
+    """pred = xn + rs * r; mean squared error against tn and its gradient dr."""
     n, c = xn.shape[:2]
     vox = xn[0, 0].numel()
     cpad = r.shape[-1]
-    _check(lib.sg_residual_loss(_p(xn), _p(tn), _p(r), n, c, vox, cpad, _p(dr), _p(loss), _p(ws), _s(stream)))
+    _check(lib.sg_residual_loss(_p(xn), _p(tn), _p(r), _p(rs), n, c, vox, cpad, _p(dr), _p(loss), _p(ws),
+                                _s(stream)))
 
 
-def unpack(xn, r, shift, scale, out=None, stream=None):
+def unpack(xn, r, shift, scale, out=None, rs=None, stream=None):
     n, c = xn.shape[:2]
     vox = xn[0, 0].numel()
     out = torch.empty_like(xn) if out is None else out
-    _check(lib.sg_unpack(_p(xn), _p(r), n, c, vox, r.shape[-1], _p(shift), _p(scale), _p(out), _s(stream)))
+    _check(lib.sg_unpack(_p(xn), _p(r), _p(rs), n, c, vox, r.shape[-1], _p(shift), _p(scale), _p(out),
+                         _s(stream)))
     return out
 
 
@@ -165,16 +167,11 @@ def phi_budget(x, out=None, stream=None):
     return out
 
 
-def cast_bf16(x, out=None, stream=None):
-    out = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device) if out is None else out
-    _check(lib.sg_cast_bf16(_p(x), x.numel(), _p(out), _s(stream)))
-    return out
-
-
 def gather(store, idx, out, stream=None):
-    """store [rows, ...] bf16, idx [n] int64 device -> out [n, ...] float."""
+    """store [rows, ...] float, idx [n] int64 device -> out [n, ...] float."""
     rows = store.shape[0]
     length = store[0].numel()
-    assert idx.dtype == torch.int64 and idx.is_cuda and out.numel() == idx.numel() * length
+    assert store.dtype == torch.float32 and idx.dtype == torch.int64 and idx.is_cuda
+    assert out.numel() == idx.numel() * length
     _check(lib.sg_gather(_p(store), rows, length, _p(idx), idx.numel(), _p(out), _s(stream)))
     return out

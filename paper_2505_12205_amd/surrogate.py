@@ -9,8 +9,8 @@ Network (the layer list below): 3 x 3 x 3 convolutions with ReLU,
 an encoder that halves the grid twice (stride 2), a bottleneck, a decoder
 that doubles it twice (nearest-neighbour upsampling fused into the
 convolution) with additive skip connections from the encoder, and a linear
-output layer whose result is added to the input (the network predicts the
-increment).  Weights are bf16 with float master copies; accumulation is
+output layer whose result, times a fixed increment scale, is added to the
+input (the network predicts the increment).  Weights are bf16 with float master copies; accumulation is
 FP32; Adam updates the master copies.  Training minimises the mean squared
 error of the normalised fields.
 
@@ -26,6 +26,13 @@ from . import nn
 
 FIELDS = ("phi", "u_x", "u_y", "u_z", "p")
 CIN = 5
+# a prediction that violates the phase-field budget by more than this
+# (relative) is handed to the solver
+FALLBACK_THRESHOLD = 1e-3
+# the network's output is multiplied by this before it is added to the
+# normalised input: one lag's increments are a few hundredths of the field
+# scales, so the last layer works with numbers of order one
+INCREMENT_SCALE = 0.05
 
 
 def layers(cin=CIN, c1=16, c2=32, c3=64):
@@ -61,7 +68,7 @@ class Network:
     """The encoder-decoder on a fixed batch shape [batch, 5, d, h, w]."""
 
     def __init__(self, batch, d, h, w, widths=(16, 32, 64), device="cuda", seed=0, lr=1e-3,
-                 u_jet=0.02, stream=None):
+                 u_jet=0.02, increment_scale=INCREMENT_SCALE, stream=None):
         self.dev = torch.device(device)
         self.stream = stream
         self.batch, self.shape = batch, (d, h, w)
@@ -71,6 +78,7 @@ class Network:
         sh, sc = norm_scales(u_jet)
         self.shift = torch.tensor(sh, device=self.dev)
         self.scale = torch.tensor(sc, device=self.dev)
+        self.rs = torch.full((CIN,), float(increment_scale), dtype=torch.float32, device=self.dev)
         # parameter layout: per layer W [co_p][27][ci_p] then b [co_p], one flat buffer
         self.lay = {}
         off = 0
@@ -184,7 +192,7 @@ class Network:
         return (self.P if buf is None else buf)[L["b"]:L["b"] + L["cop"]]
 
     def save(self, path):
-        np.savez(path, **self.get_params())
+        np.savez(path, **{k: v.astype(np.float32) for k, v in self.get_params().items()})
 
     def load(self, path):
         with np.load(path, allow_pickle=False) as z:
@@ -238,7 +246,7 @@ class Network:
         device scalar of the loss (before the update)."""
         r = self.forward(xn)
         nn.residual_loss(xn, tn, r, self.dz["out"], self.loss if with_loss else None, self.loss_ws,
-                         stream=self.stream)
+                         rs=self.rs, stream=self.stream)
         self.backward()
         self.step()
         return self.loss
@@ -246,7 +254,7 @@ class Network:
     def loss_and_grad(self, xn, tn):
         """Loss and gradients without an update (G holds the gradients)."""
         r = self.forward(xn)
-        nn.residual_loss(xn, tn, r, self.dz["out"], self.loss, self.loss_ws, stream=self.stream)
+        nn.residual_loss(xn, tn, r, self.dz["out"], self.loss, self.loss_ws, rs=self.rs, stream=self.stream)
         self.backward()
         return self.loss
 
@@ -254,7 +262,7 @@ class Network:
         """Physical fields at t + the training lag from physical fields x."""
         xn = self.normalize(x)
         r = self.forward(xn)
-        return nn.unpack(xn, r, self.shift, self.scale, out=out, stream=self.stream)
+        return nn.unpack(xn, r, self.shift, self.scale, out=out, rs=self.rs, stream=self.stream)
 
     def grads(self):
         """Gradients in the layout of get_params (host float64)."""
@@ -268,13 +276,23 @@ class Network:
         return out
 
 
-def mass_drift(x, pred, lag=32):
+def phase_mass(x):
+    """Sum of phi per sample, FP64 (host array)."""
+    return nn.phi_budget(x).cpu().numpy()[:, 0]
+
+
+def mass_drift(x_prev, x, pred):
     """Relative violation of the phase-field budget by a prediction: the
-    change of sum phi over the window minus what the inlet and last planes
-    carried in and out over `lag` fine steps (coarse cells hold 8 fine
-    cells, a coarse face 4), relative to sum phi of the input.
-    x, pred: physical coarse fields [n, 5, d, h, w]; returns [n] (host)."""
-    a = nn.phi_budget(x).cpu().numpy()
-    b = nn.phi_budget(pred).cpu().numpy()
-    flux = 0.5 * lag * (a[:, 1] - a[:, 2] + b[:, 1] - b[:, 2]) * 4.0 / 8.0
-    return np.abs(b[:, 0] - a[:, 0] - flux) / np.abs(a[:, 0])
+    jet's liquid content changes by what the inlet injects less what leaves,
+    which varies slowly from one lag to the next, so the predicted change
+    sum(pred) - sum(x) is compared with the change over the previous lag,
+    sum(x) - sum(x_prev), relative to sum(x).  All states are physical
+    coarse fields [n, 5, d, h, w] one lag apart; returns [n] (host)."""
+    m0, m1, m2 = phase_mass(x_prev), phase_mass(x), phase_mass(pred)
+    return np.abs((m2 - m1) - (m1 - m0)) / np.abs(m1)
+
+
+def fallback_mask(x_prev, x, pred, threshold=FALLBACK_THRESHOLD):
+    """Samples whose prediction violates the phase-field budget by more
+    than `threshold` (relative): the solver advances those instead."""
+    return mass_drift(x_prev, x, pred) > threshold

@@ -164,15 +164,25 @@ def sweep_weber(n=64, lo=0.5, hi=8.0):
     return lo * (hi / lo) ** (np.arange(n) / (n - 1))
 
 
+SWEEP_MOBILITY = 0.05
+
+
 def jet_sweep(n=64, nx=96, ny=96, radius=8.0, reynolds=200.0, lengths=None, webers=None,
-              seed=12205):
-    """The batched sweep: a list of (cfg, phi0, u0) jet domains of uneven length."""
+              seed=12205, mobility=SWEEP_MOBILITY, **kw):
+    """The batched sweep: a list of (cfg, phi0, u0) jet domains of uneven length.
+
+    The sweep's configuration fixes Re, We, the density ratio and the nozzle
+    radius but not the mobility.  With M = 0.01 (the precision-form jet's
+    value) the low-We end diverges within a few hundred steps in the FP64
+    reference and on the GPU alike (at R = 8 and Re = 200 the grid Ohnesorge
+    number sqrt(D We)/Re is 0.014 at We = 0.5); M = 0.05 (Peclet number
+    u_j D / M = 6.4) keeps every Weber number of the sweep stable."""
     L = sweep_lengths(seed, n) if lengths is None else lengths
     We = sweep_weber(n) if webers is None else webers
     out = []
     for k in range(len(L)):
         out.append(jet3d(nx=nx, ny=ny, nz=int(L[k]), radius=radius, reynolds=reynolds,
-                         weber=float(We[k])))
+                         weber=float(We[k]), mobility=mobility, **kw))
     return out
 
 
@@ -191,5 +201,5 @@ def summary(cfg):
                      for k in keys if k in cfg)
 
 
-__all__ = ["drop2d", "rt3d", "rt_params", "jet3d", "jet_params", "jet_sweep", "sweep_lengths",
+__all__ = ["drop2d", "rt3d", "rt_params", "jet3d", "jet_params", "jet_sweep", "SWEEP_MOBILITY", "sweep_lengths",
            "sweep_weber", "perturb", "phi_in_profile", "summary"]

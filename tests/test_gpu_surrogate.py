@@ -187,8 +187,8 @@ def test_adam_matches_oracle():
     assert (pb.float().cpu().numpy() == _bf(got)).all()
 
 
-def _net_case(torch, surrogate, widths=(16, 32, 16), shape=(8, 8, 12), batch=2, seed=3):
-    net = surrogate.Network(batch, *shape, widths=widths, seed=seed)
+def _net_case(torch, surrogate, widths=(16, 32, 16), shape=(8, 8, 12), batch=2, seed=3, scale=1.0):
+    net = surrogate.Network(batch, *shape, widths=widths, seed=seed, increment_scale=scale)
     params = net.get_params()
     rng = np.random.default_rng(seed)
     for k in params:  # bf16-representable weights, non-zero biases
@@ -206,7 +206,7 @@ def test_network_loss_and_gradients_match_oracle():
     torch, nn, surrogate = _mods()
     net, params, x, t = _net_case(torch, surrogate)
     spec = S.layers(5, *(16, 32, 16))
-    Lo, Go = S.loss_and_grad(params, spec, x, t)
+    Lo, Go = S.loss_and_grad(params, spec, x, t, net.rs[0].item())
     xn = torch.tensor(x, dtype=torch.float32, device="cuda")
     tn = torch.tensor(t, dtype=torch.float32, device="cuda")
     _log("[gpu] network loss and gradients")
@@ -225,7 +225,7 @@ def test_network_loss_and_gradients_match_oracle():
         assert rel <= 6e-2 and cos >= 0.998, k
     # discrimination: an oracle without the skip connections is far outside the bound
     bad = [(n, ci, co, s_, u_, r_, None) for (n, ci, co, s_, u_, r_, _) in spec]
-    _, Gb = S.loss_and_grad(params, bad, x, t)
+    _, Gb = S.loss_and_grad(params, bad, x, t, net.rs[0].item())
     worst = max(rel_cos(Gg[k], Gb[k])[0] for k in Gb)
     _log(f"against the mis-wired oracle: worst rel L2 {worst:.3e}")
     assert worst > 0.3
@@ -235,7 +235,7 @@ def test_training_lowers_the_loss():
     torch, nn, surrogate = _mods()
     rng = np.random.default_rng(11)
     batch, shape = 4, (16, 16, 16)
-    net = surrogate.Network(batch, *shape, seed=1, lr=2e-3)
+    net = surrogate.Network(batch, *shape, seed=1, lr=2e-3, increment_scale=1.0)
     # a learnable map: the target is the input advected by one cell along z
     x = rng.standard_normal((batch, 5) + shape).astype(np.float32)
     t = np.roll(x, 1, axis=2) * 0.9
@@ -248,3 +248,33 @@ def test_training_lowers_the_loss():
     _log(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert np.isfinite(losses).all()
     assert losses[-1] < 0.6 * losses[0]
+
+
+def test_network_increment_scale():
+    """The production increment scale (0.05) enters the prediction and the
+    loss gradient: loss and the output layer's gradients against the oracle
+    with the same scale (the layers below are covered at scale 1)."""
+    torch, nn, surrogate = _mods()
+    net, params, x, t = _net_case(torch, surrogate, scale=surrogate.INCREMENT_SCALE, seed=5)
+    spec = S.layers(5, *(16, 32, 16))
+    Lo, Go = S.loss_and_grad(params, spec, x, t, surrogate.INCREMENT_SCALE)
+    xn = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tn = torch.tensor(t, dtype=torch.float32, device="cuda")
+    _log("[gpu] network increment scale")
+    Lg = float(net.loss_and_grad(xn, tn).item())
+    Gg = net.grads()
+    assert abs(Lg - Lo) <= 1e-3 * Lo
+    for k in ("out.w", "out.b", "d4.w"):
+        a, b = Gg[k].ravel(), Go[k].ravel()
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        _log(f"scale {surrogate.INCREMENT_SCALE}: grad {k} rel L2 {rel:.3e}")
+        assert rel <= 2e-2, k
+    # predict() takes physical fields and returns physical fields
+    sh, sc = surrogate.norm_scales()
+    sc5 = sc[None, :, None, None, None].astype(np.float64)
+    phys = torch.tensor(x / sc5, dtype=torch.float32, device="cuda")
+    pred = net.predict(phys).cpu().numpy().astype(np.float64) * sc5
+    po, _ = S.forward(params, spec, x, surrogate.INCREMENT_SCALE)
+    e = np.abs(pred - po).max()
+    _log(f"predict() in normalised units: max err {e:.3e}")
+    assert e < 2e-2
