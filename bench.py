@@ -79,6 +79,44 @@ def run_batch(steps, warmup, storage="fp16", autotune=True, launch=None):
     return bt.nodes, dt, kt, lb
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16, published
+
+
+def run_surrogate(steps=10, batch=32):
+    """Training-step and forward throughput of the surrogate (batch 32 of
+    5 x 192 x 48 x 48 coarse windows) in TFLOP/s of executed MFMA work."""
+    import torch
+
+    from paper_2505_12205_amd import surrogate as SG
+    net = SG.Network(batch, 192, 48, 48, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((batch, 5, 192, 48, 48), device="cuda", generator=g) * 0.1
+    t = x + 0.01 * torch.randn(x.shape, device="cuda", generator=g)
+    fl = 0
+    for (name, *_r) in net.spec:
+        L = net.lay[name]
+        od, oh, ow = [-(-(L["u"] * e) // L["s"]) for e in net.ext_in[name]]
+        fl += 2 * batch * od * oh * ow * L["cip"] * L["cop"] * 27
+    for _ in range(3):
+        net.train_step(x, t, with_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x, t, with_loss=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    df = (time.perf_counter() - t0) / steps
+    return {"train_step_ms": round(dt * 1e3, 2), "train_TFLOPs": round(3 * fl / dt / 1e12, 1),
+            "forward_ms": round(df * 1e3, 2), "forward_TFLOPs": round(fl / df / 1e12, 1),
+            "forward_flop": fl, "mfma_bf16_peak_TFLOPs": MFMA_BF16_PEAK_TFLOPS,
+            "train_frac": round(3 * fl / dt / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4),
+            "batch": batch, "window": [5, 192, 48, 48]}
+
+
 def counted_traffic():
     """HBM bytes per launch of the fused FP32 step from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
@@ -150,6 +188,7 @@ def main():
     ap.add_argument("--tile", default="", help="bx,by launch shape of the fused kernel")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Weber sweep")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training step")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
     ap.add_argument("--blocks-per-cu", type=int, default=8, help="batched launch with --tile")
@@ -216,6 +255,11 @@ def main():
                                  "outlet_ms": round(ktb[2], 4),
                                  "intact_length_range": [min(lb), max(lb)]}
         print(f"[bench] batched_fp16 {forms['batched_fp16']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
+    if not args.no_surrogate:
+        forms["surrogate_bf16_mfma"] = run_surrogate()
+        print(f"[bench] surrogate {forms['surrogate_bf16_mfma']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
     traffic, traffic_src = counted_traffic()

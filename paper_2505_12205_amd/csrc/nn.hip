@@ -1,13 +1,14 @@
 // nn.hip -- gfx950 kernels of the learned surrogate (include/surrogate.h).
 //
-// The convolutions are implicit GEMMs on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation):
+// The convolutions are implicit GEMMs on the bf16 matrix cores (FP32
+// accumulation; v_mfma_f32_16x16x32_bf16 for the forward and data gradient,
+// v_mfma_f32_16x16x16_bf16 for the weight gradient):
 //   forward      M = output voxels, N = co, K = 27 taps x ci
 //   data grad    M = input voxels,  N = ci, K = 27 taps x (up^3 sub-positions) x co
 //   weight grad  M = co, N = ci (one tap per block row), K = output voxels
-// Activations are NDHWC bf16 with 16 | C, so one MFMA K-slice is one tap
-// and 16 contiguous channels: every lane reads its 4 operand values with a
-// single 8-byte load.  A wave owns 16*MS voxels x 16*NS channels with
+// Activations are NDHWC bf16 with 16 | C, so every lane reads its operand
+// values (8 consecutive K entries: channels of one tap) with one 16-byte
+// load.  A wave owns 16*MS voxels x 16*NS channels with
 // MS * NS = 8 accumulator tiles.  The weight gradient stages 64-voxel tiles
 // of dz and of the gathered input in LDS, transposed so that the voxel
 // (reduction) index is contiguous.
@@ -49,6 +50,15 @@ __device__ __forceinline__ v4s ld4(const uint16_t* p) { return *(const v4s*)p; }
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+
+// gfx950's 16 x 16 x 32 form: every lane holds 8 consecutive K values of its
+// A row and of its B column (K index 8 (lane / 16) + j), D as above
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v8bf ld8(const uint16_t* p) { return *(const v8bf*)p; }
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 struct Geo {
   int n, d, h, w;    // layer input extent
@@ -105,33 +115,34 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
   for (int m = 0; m < MS; ++m)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
-  const v4s zero = {0, 0, 0, 0};
+  const v8bf zero = {};
   const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
-  for (int kz = 0; kz < 3; ++kz)
-    for (int ky = 0; ky < 3; ++ky)
-      for (int kx = 0; kx < 3; ++kx) {
-        const int tap = (kz * 3 + ky) * 3 + kx;
-        long long src[MS];
-        bool in[MS];
+  // K = 27 taps x ci, tap-major; a 32-wide K chunk gives each lane 8
+  // channels of one tap (16 | ci)
+  const int K = 27 * g.ci, csh = ilog2(g.ci);
+  auto load = [&](int k0, v8bf* a, v8bf* b) {
+    const int k = k0 + 8 * quad;
+    const bool kin = k < K;
+    const int tap = kin ? (k >> csh) : 0, c = k - (tap << csh);
+    const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
 #pragma unroll
-        for (int m = 0; m < MS; ++m) {
-          const int qz = pz[m] * S + kz - 1, qy = py[m] * S + ky - 1, qx = px[m] * S + kx - 1;
-          in[m] = ok[m] && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
-          src[m] = in[m] ? ((((long long)nb[m] * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * g.ci : 0;
-        }
-        const uint16_t* wrow = wgt + (long long)tap * g.ci + 4 * quad;
-        for (int c0 = 0; c0 < g.ci; c0 += 16) {
-          v4s a[MS];
+    for (int m = 0; m < MS; ++m) {
+      const int qz = pz[m] * S + kz - 1, qy = py[m] * S + ky - 1, qx = px[m] * S + kx - 1;
+      const bool in = kin && ok[m] && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+      a[m] = in ? ld8(x + ((((long long)nb[m] * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * g.ci + c)
+                : zero;
+    }
 #pragma unroll
-          for (int m = 0; m < MS; ++m) a[m] = in[m] ? ld4(x + src[m] + c0 + 4 * quad) : zero;
+    for (int s = 0; s < NS; ++s) b[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : zero;
+  };
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    v8bf a[MS], b[NS];
+    load(k0, a, b);
 #pragma unroll
-          for (int s = 0; s < NS; ++s) {
-            const v4s b = ld4(wrow + (long long)(s * 16 + col) * 27 * g.ci + c0);
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int m = 0; m < MS; ++m) acc[m][s] = mfma(a[m], b, acc[m][s]);
-          }
-        }
-      }
+      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+  }
   // lane holds D[4 quad + r][col]: voxel row 4 quad + r, channel col
 #pragma unroll
   for (int m = 0; m < MS; ++m)
@@ -185,40 +196,39 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
   for (int m = 0; m < MS; ++m)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
-  const v4s zero = {0, 0, 0, 0};
-  for (int kz = 0; kz < 3; ++kz)
-    for (int ky = 0; ky < 3; ++ky)
-      for (int kx = 0; kx < 3; ++kx) {
-        const int tap = (kz * 3 + ky) * 3 + kx;
-        const uint16_t* wrow = wt + (long long)tap * CI * g.co + 4 * quad;
-        for (int j = 0; j < U * U * U; ++j) {  // sub-position of the upsampled input
-          const int jz = j / (U * U), jy = (j / U) % U, jx = j % U;
-          long long src[MS];
-          bool in[MS];
+  const v8bf zero = {};
+  // K = 27 taps x U^3 sub-positions x co; a 32-wide chunk gives each lane 8
+  // channels of one (tap, sub-position) (16 | co)
+  constexpr int U3 = U * U * U;
+  const int K = 27 * U3 * g.co, osh = ilog2(g.co);
+  auto load = [&](int k0, v8bf* a, v8bf* b) {
+    const int k = k0 + 8 * quad;
+    const bool kin = k < K;
+    const int tj = kin ? (k >> osh) : 0, o = k - (tj << osh);
+    const int tap = tj / U3, j = tj % U3;
+    const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+    const int jz = j / (U * U), jy = (j / U) % U, jx = j % U;
 #pragma unroll
-          for (int m = 0; m < MS; ++m) {
-            // virtual input position q = r U + j is read by output p when s p + k - 1 = q
-            const int tz = rz[m] * U + jz + 1 - kz, ty = ry[m] * U + jy + 1 - ky, tx = rx[m] * U + jx + 1 - kx;
-            bool v = ok[m] && tz >= 0 && ty >= 0 && tx >= 0;
-            if (S == 2) v = v && !(tz & 1) && !(ty & 1) && !(tx & 1);
-            const int ppz = tz / S, ppy = ty / S, ppx = tx / S;
-            v = v && ppz < g.od && ppy < g.oh && ppx < g.ow;
-            in[m] = v;
-            src[m] = v ? ((((long long)nb[m] * g.od + ppz) * g.oh + ppy) * g.ow + ppx) * g.co : 0;
-          }
-          for (int c0 = 0; c0 < g.co; c0 += 16) {
-            v4s a[MS];
+    for (int m = 0; m < MS; ++m) {
+      // virtual input position q = r U + j is read by output p when s p + k - 1 = q
+      const int tz = rz[m] * U + jz + 1 - kz, ty = ry[m] * U + jy + 1 - ky, tx = rx[m] * U + jx + 1 - kx;
+      bool v = kin && ok[m] && tz >= 0 && ty >= 0 && tx >= 0;
+      if (S == 2) v = v && !(tz & 1) && !(ty & 1) && !(tx & 1);
+      const int ppz = tz / S, ppy = ty / S, ppx = tx / S;
+      v = v && ppz < g.od && ppy < g.oh && ppx < g.ow;
+      a[m] = v ? ld8(dz + ((((long long)nb[m] * g.od + ppz) * g.oh + ppy) * g.ow + ppx) * g.co + o) : zero;
+    }
 #pragma unroll
-            for (int m = 0; m < MS; ++m) a[m] = in[m] ? ld4(dz + src[m] + c0 + 4 * quad) : zero;
+    for (int s = 0; s < NS; ++s) b[s] = kin ? ld8(wt + ((long long)tap * CI + s * 16 + col) * g.co + o) : zero;
+  };
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    v8bf a[MS], b[NS];
+    load(k0, a, b);
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-              const v4s b = ld4(wrow + (long long)(s * 16 + col) * g.co + c0);
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-              for (int m = 0; m < MS; ++m) acc[m][s] = mfma(a[m], b, acc[m][s]);
-            }
-          }
-        }
-      }
+      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+  }
 #pragma unroll
   for (int m = 0; m < MS; ++m)
 #pragma unroll
@@ -242,6 +252,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
 // weight gradient: block (chunk, tap) sums dz[v, o] X[src(v, tap), c] over
 // its voxel chunk; partial[chunk][tap][o][c]; db partials from tap 0 blocks
 // ---------------------------------------------------------------------------
+constexpr int kAllTapsMaxTiles = 2;  // larger (co, ci) take one tap per block
 constexpr int WV = 64;       // voxels per LDS tile
 constexpr int WP = WV + 8;   // padded LDS row (bf16 elements)
 
@@ -357,20 +368,140 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
       for (int r = 0; r < 4; ++r) dbpart[(long long)chunk * CO + ot * 16 + 4 * quad + r] = accb[ot][r];
 }
 
-__global__ void k_bwd_w_reduce(const float* __restrict__ part, const float* __restrict__ dbpart, int nchunk, int co,
-                               int ci, float* __restrict__ dw, float* __restrict__ db) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [tap][o][c]
-  const int n = 27 * co * ci;
-  if (i < n) {
-    float s = 0.0f;
-    for (int k = 0; k < nchunk; ++k) s += part[(long long)k * n + i];
-    const int c = i % ci, o = (i / ci) % co, tap = i / (ci * co);
-    dw[((long long)o * 27 + tap) * ci + c] = s;
+// Weight gradient for small channel counts ((CO/16) (CI/16) <= 2): a block
+// owns a voxel chunk and all 27 taps, so its dz tile is staged once; wave w
+// takes taps w, w + 4, ... (whole 64-voxel tiles), so no cross-wave sums are
+// needed.  Partials as in k_conv_bwd_w (grid.y = 1, tap index inside).
+template <int CO, int CI, int S, int U>
+__global__ __launch_bounds__(256) void k_conv_bwd_w_taps(const uint16_t* __restrict__ x,
+                                                         const uint16_t* __restrict__ dz, Geo g, long long vchunk,
+                                                         float* __restrict__ part, float* __restrict__ dbpart) {
+  constexpr int NO = CO / 16, NC = CI / 16, NTL = NO * NC, SLOTS = 7;  // ceil(27 / 4)
+  __shared__ __attribute__((aligned(16))) uint16_t dzT[CO * WP];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[4][CI * WP];
+  const int chunk = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  const long long v0 = (long long)chunk * vchunk;
+  const long long v1 = v0 + vchunk < g.mo ? v0 + vchunk : g.mo;
+  v4f acc[SLOTS][NTL], accb[NO];
+#pragma unroll
+  for (int t = 0; t < SLOTS; ++t)
+#pragma unroll
+    for (int i = 0; i < NTL; ++i) acc[t][i] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NO; ++t) accb[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const short one = 0x3F80;  // bf16 1.0
+  const v4s ones = {one, one, one, one};
+  const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
+  uint16_t* myx = xT[wv];
+  for (long long vt = v0; vt < v1; vt += WV) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < WV * (CO / 4); i += 256) {
+      const int vl = i / (CO / 4), c4 = (i % (CO / 4)) * 4;
+      const long long v = vt + vl;
+      v4s val = {0, 0, 0, 0};
+      if (v < v1) val = ld4(dz + v * CO + c4);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dzT[(c4 + j) * WP + vl] = (uint16_t)val[j];
+    }
+    // this lane's voxel decomposition for the gathers (lane = voxel of the tile)
+    long long vv = vt + lane;
+    const bool vok = vv < v1;
+    if (!vok) vv = v0;
+    const int px = (int)(vv % g.ow);
+    vv /= g.ow;
+    const int py = (int)(vv % g.oh);
+    vv /= g.oh;
+    const int pz = (int)(vv % g.od);
+    const int n = (int)(vv / g.od);
+#pragma unroll
+    for (int slot = 0; slot < SLOTS; ++slot) {
+      const int tap = wv + 4 * slot;
+      __syncthreads();  // dzT ready (slot 0) / previous slot's reads done
+      if (tap < 27) {
+        const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+        const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
+        const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+        const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
+                                   (in ? qx / U : 0)) * CI;
+#pragma unroll
+        for (int c4 = 0; c4 < CI; c4 += 4) {
+          const v4s val = in ? ld4(src + c4) : (v4s){0, 0, 0, 0};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) myx[(c4 + j) * WP + lane] = (uint16_t)val[j];
+        }
+      }
+      __syncthreads();
+      if (tap < 27) {
+#pragma unroll
+        for (int kk = 0; kk < WV / 16; ++kk) {
+          const int kofs = kk * 16 + 4 * quad;
+          v4s a[NO], b[NC];
+#pragma unroll
+          for (int t = 0; t < NO; ++t) a[t] = *(const v4s*)&dzT[(t * 16 + col) * WP + kofs];
+#pragma unroll
+          for (int t = 0; t < NC; ++t) b[t] = *(const v4s*)&myx[(t * 16 + col) * WP + kofs];
+#pragma unroll
+          for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+            for (int ct = 0; ct < NC; ++ct) acc[slot][ot * NC + ct] = mfma(a[ot], b[ct], acc[slot][ot * NC + ct]);
+          if (slot == 0 && wv == 0)
+#pragma unroll
+            for (int ot = 0; ot < NO; ++ot) accb[ot] = mfma(a[ot], ones, accb[ot]);
+        }
+      }
+    }
   }
-  if (i < co) {
-    float s = 0.0f;
-    for (int k = 0; k < nchunk; ++k) s += dbpart[(long long)k * co + i];
-    db[i] = s;
+#pragma unroll
+  for (int slot = 0; slot < SLOTS; ++slot) {
+    const int tap = wv + 4 * slot;
+    if (tap >= 27) break;
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int o = ot * 16 + 4 * quad + r, c = ct * 16 + col;
+          part[(((long long)chunk * 27 + tap) * CO + o) * CI + c] = acc[slot][ot * NC + ct][r];
+        }
+  }
+  if (wv == 0 && col == 0)
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dbpart[(long long)chunk * CO + ot * 16 + 4 * quad + r] = accb[ot][r];
+}
+
+// dw[o][k][c] = sum over chunks of part[chunk][k][o][c] (and db likewise):
+// a block takes 64 consecutive outputs, its four waves every fourth chunk,
+// and the four partial sums are added in wave order (deterministic)
+__global__ __launch_bounds__(256) void k_bwd_w_reduce(const float* __restrict__ part,
+                                                      const float* __restrict__ dbpart, int nchunk, int co, int ci,
+                                                      float* __restrict__ dw, float* __restrict__ db) {
+  __shared__ float sh[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = 27 * co * ci;
+  const int nb = (n + 63) / 64;
+  const bool bias = blockIdx.x == nb;  // the last block sums the bias partials
+  const int i = blockIdx.x * 64 + lane;
+  float s = 0.0f;
+  if (bias) {
+    if (lane < co)
+      for (int k = wv; k < nchunk; k += 4) s += dbpart[(long long)k * co + lane];
+  } else if (i < n) {
+    for (int k = wv; k < nchunk; k += 4) s += part[(long long)k * n + i];
+  }
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0) return;
+  const float t = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (bias) {
+    if (lane < co) db[lane] = t;
+  } else if (i < n) {
+    const int c = i % ci, o = (i / ci) % co, tap = i / (ci * co);
+    dw[((long long)o * 27 + tap) * ci + c] = t;
   }
 }
 
@@ -567,16 +698,23 @@ void launch_bwd_data_su(const Geo& g, const uint16_t* dz, const uint16_t* wt, co
   else launch_bwd_data<64, S, U>(g, dz, wt, add, mask, da, dzp, st);
 }
 
+template <int CO, int CI, int S, int U>
+void launch_bwd_w_one(const Geo& g, const uint16_t* x, const uint16_t* dz, int nchunk, long long vchunk,
+                      float* part, float* dbpart, hipStream_t st) {
+  if constexpr ((CO / 16) * (CI / 16) <= kAllTapsMaxTiles)  // all taps per block
+    hipLaunchKernelGGL((k_conv_bwd_w_taps<CO, CI, S, U>), dim3(nchunk), dim3(256), 0, st, x, dz, g, vchunk, part,
+                       dbpart);
+  else
+    hipLaunchKernelGGL((k_conv_bwd_w<CO, CI, S, U>), dim3(nchunk, 27), dim3(256), 0, st, x, dz, g, vchunk, part,
+                       dbpart);
+}
+
 template <int CO, int S, int U>
 void launch_bwd_w_co(const Geo& g, const uint16_t* x, const uint16_t* dz, int nchunk, long long vchunk,
                      float* part, float* dbpart, hipStream_t st) {
-  const dim3 grid(nchunk, 27);
-  if (g.ci == 16)
-    hipLaunchKernelGGL((k_conv_bwd_w<CO, 16, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
-  else if (g.ci == 32)
-    hipLaunchKernelGGL((k_conv_bwd_w<CO, 32, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
-  else
-    hipLaunchKernelGGL((k_conv_bwd_w<CO, 64, S, U>), grid, dim3(256), 0, st, x, dz, g, vchunk, part, dbpart);
+  if (g.ci == 16) launch_bwd_w_one<CO, 16, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else if (g.ci == 32) launch_bwd_w_one<CO, 32, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  else launch_bwd_w_one<CO, 64, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
 }
 
 template <int S, int U>
@@ -587,9 +725,11 @@ void launch_bwd_w_su(const Geo& g, const uint16_t* x, const uint16_t* dz, int nc
   else launch_bwd_w_co<64, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
 }
 
-// voxel chunking of the weight gradient: about 2048 blocks over the 27 taps
+// voxel chunking of the weight gradient: about 2048 blocks (the per-tap
+// kernel has 27 blocks per chunk, the all-taps kernel one)
 void wchunks(const Geo& g, int& nchunk, long long& vchunk) {
-  const long long target = 76;
+  const bool all_taps = (g.co / 16) * (g.ci / 16) <= kAllTapsMaxTiles;
+  const long long target = all_taps ? 2048 : 76;
   long long vc = (g.mo + target - 1) / target;
   vc = ((vc + WV - 1) / WV) * WV;
   if (vc < WV) vc = WV;
@@ -667,7 +807,7 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
   else if (stride == 2) launch_bwd_w_su<2, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   else launch_bwd_w_su<1, 2>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   const int nred = 27 * co * ci;
-  hipLaunchKernelGGL(k_bwd_w_reduce, dim3(blocks_for(nred, 256)), dim3(256), 0, st, part, dbpart, nchunk, co, ci,
+  hipLaunchKernelGGL(k_bwd_w_reduce, dim3((nred + 63) / 64 + 1), dim3(256), 0, st, part, dbpart, nchunk, co, ci,
                      dw, db);
   return check_launch("sg_conv3d_bwd_weight");
 }
