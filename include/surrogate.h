@@ -90,13 +90,18 @@ int sg_normalize(const float* x, int n, int c, long long vox, const float* shift
 int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb, void* stream);
 
 /* Residual loss: pred = xn + rs[c] r[..., c] (rs: device array of c
- * increment scales, null for ones), L = mean over n c vox of (pred - tn)^2.
- * r [n, vox, cpad] bf16 (the last layer's output); writes dr [n, vox, cpad]
- * = dL/dr (zero in the padding channels) and, if loss is non-null, L as a
- * double.  ws (required): device workspace of 1024 doubles for the FP64
- * partial sums, added in a fixed order. */
+ * increment scales, null for ones), d = pred - tn,
+ *   L = mean over n c vox of d^2 + mass_weight * mean_n (S_n / vox)^2,
+ * S_n the sum of d over the voxels of channel 0 (the phase field) of sample
+ * n: the second term asks the prediction to carry the phase-field content
+ * of the target.  r [n, vox, cpad] bf16 (the last layer's output); writes
+ * dr [n, vox, cpad] = dL/dr (zero in the padding channels) and, if loss is
+ * non-null, L as a double.  ws (required): device workspace of 2048 doubles
+ * (FP64 partial sums added in a fixed order, then the per-sample sums);
+ * mass_weight >= 0, and n <= 1024 when it is positive. */
 int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, const float* rs, int n, int c,
-                     long long vox, int cpad, uint16_t* dr, double* loss, void* ws, void* stream);
+                     long long vox, int cpad, float mass_weight, uint16_t* dr, double* loss, void* ws,
+                     void* stream);
 
 /* Prediction in physical units:
  * out[n, c, vox] = (xn + rs[c] r[..., c]) / scale[c] + shift[c] (rs nullable). */

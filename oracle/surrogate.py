@@ -17,7 +17,9 @@ optimiser are this project's own definitions, written out plainly here:
 * relu(z) = max(z, 0); skip connections add a stored activation after the
   relu; the output is the input plus the last (linear) layer times a fixed
   increment scale: x + scale r(x).
-* loss = mean over all elements of (prediction - target)^2.
+* loss = mean over all elements of (prediction - target)^2, optionally plus
+  a weight times the mean over samples of the squared mean residual of the
+  phase field (channel 0).
 * Adam with bias correction (Kingma & Ba, Algorithm 1).
 
 Everything is float64 numpy: np.einsum over the channel axis is the only
@@ -175,9 +177,20 @@ def forward(P, spec, x, scale=1.0):
     return x + scale * h, cache
 
 
-def mse(pred, target):
+def mse(pred, target, mass_weight=0.0):
+    """Mean squared error, plus mass_weight * mean over samples of the
+    squared mean phase-field residual (channel 0): the prediction should
+    carry the target's phase-field content.  Returns (L, dL/dpred)."""
     d = pred - target
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    L = float(np.mean(d * d))
+    g = 2.0 * d / d.size
+    if mass_weight:
+        N = d.shape[0]
+        V = d[0, 0].size
+        m = d[:, 0].reshape(N, -1).sum(axis=1) / V  # mean residual of phi per sample
+        L += mass_weight * float(np.mean(m * m))
+        g[:, 0] += (mass_weight * 2.0 * m / (N * V))[:, None, None, None]
+    return L, g
 
 
 def backward(P, spec, cache, dpred, scale=1.0):
@@ -198,9 +211,9 @@ def backward(P, spec, cache, dpred, scale=1.0):
     return G, dh + dpred  # d/dx includes the identity path
 
 
-def loss_and_grad(P, spec, x, target, scale=1.0):
+def loss_and_grad(P, spec, x, target, scale=1.0, mass_weight=0.0):
     pred, cache = forward(P, spec, x, scale)
-    L, dpred = mse(pred, target)
+    L, dpred = mse(pred, target, mass_weight)
     G, _ = backward(P, spec, cache, dpred, scale)
     return L, G
 

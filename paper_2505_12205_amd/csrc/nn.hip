@@ -560,11 +560,31 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 constexpr int kLossBlocks = 1024;
+constexpr int kLossMaxSamples = 1024;  // mass term: per-sample sums follow the partials in ws
+
+// per-sample sum of the phase-field residual d = xn + rs r - tn (channel 0),
+// FP64, one block per sample (fixed order)
+__global__ __launch_bounds__(256) void k_mass_residual(const float* __restrict__ xn, const float* __restrict__ tn,
+                                                       const uint16_t* __restrict__ r,
+                                                       const float* __restrict__ rs, int c, long long vox,
+                                                       int cpad, double* __restrict__ msum) {
+  __shared__ double sh[4];
+  const long long n = blockIdx.x;
+  const float sc = rs ? rs[0] : 1.0f;
+  double s = 0.0;
+  for (long long v = threadIdx.x; v < vox; v += blockDim.x) {
+    const long long j = n * c * vox + v;
+    s += (double)(xn[j] + sc * bf2f(r[(n * vox + v) * cpad]) - tn[j]);
+  }
+  const double b = block_sum(s, sh);
+  if (threadIdx.x == 0) msum[n] = b;
+}
 
 __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__ xn, const float* __restrict__ tn,
                                                        const uint16_t* __restrict__ r,
                                                        const float* __restrict__ rs, int c, long long vox,
                                                        int cpad, long long total, float inv_count,
+                                                       const double* __restrict__ msum, float mgrad,
                                                        uint16_t* __restrict__ dr, double* __restrict__ part) {
   __shared__ double sh[4];
   double s = 0.0;
@@ -578,7 +598,9 @@ __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__
       const float sc = rs ? rs[ch] : 1.0f;
       const float d = xn[j] + sc * bf2f(r[i]) - tn[j];
       s += (double)d * d;
-      gval = 2.0f * sc * d * inv_count;
+      float gd = 2.0f * d * inv_count;
+      if (msum && ch == 0) gd += mgrad * (float)msum[n];  // d/dd of the mass term
+      gval = sc * gd;
     }
     dr[i] = f2bf(gval);
   }
@@ -586,11 +608,19 @@ __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-__global__ void k_sum_parts(const double* __restrict__ part, int n, double scale, double* out) {
+// loss = scale * sum(part) + mw * sum_n (msum[n] / vox)^2 / n (mass term, if msum)
+__global__ void k_sum_parts(const double* __restrict__ part, int np, double scale, const double* __restrict__ msum,
+                            int n, double vox, double mw, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s * scale;
+    for (int i = 0; i < np; ++i) s += part[i];
+    s *= scale;
+    if (msum) {
+      double m = 0.0;
+      for (int i = 0; i < n; ++i) m += (msum[i] / vox) * (msum[i] / vox);
+      s += mw * m / n;
+    }
+    *out = s;
   }
 }
 
@@ -848,16 +878,26 @@ int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb
 }
 
 int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, const float* rs, int n, int c,
-                     long long vox, int cpad, uint16_t* dr, double* loss, void* ws, void* stream) {
-  if (!xn || !tn || !r || !dr || !ws || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c)
+                     long long vox, int cpad, float mass_weight, uint16_t* dr, double* loss, void* ws,
+                     void* stream) {
+  if (!xn || !tn || !r || !dr || !ws || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c ||
+      !(mass_weight >= 0.0f))
     return fail(SG_EINVAL, "bad loss arguments");
+  if (mass_weight > 0.0f && n > kLossMaxSamples) return fail(SG_EINVAL, "mass term: too many samples");
   const long long total = (long long)n * vox * cpad;
   const double count = (double)n * c * vox;
   hipStream_t st = (hipStream_t)stream;
   double* part = (double*)ws;
+  double* msum = mass_weight > 0.0f ? part + kLossBlocks : nullptr;
+  if (msum)
+    hipLaunchKernelGGL(k_mass_residual, dim3(n), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, msum);
+  // d/dd of mw * mean_n (S_n / V)^2 is 2 mw S_n / (n V^2)
+  const float mgrad = (float)(2.0 * mass_weight / ((double)n * (double)vox * (double)vox));
   hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, total,
-                     (float)(1.0 / count), dr, part);
-  if (loss) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kLossBlocks, 1.0 / count, loss);
+                     (float)(1.0 / count), msum, mgrad, dr, part);
+  if (loss)
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kLossBlocks, 1.0 / count, msum, n,
+                       (double)vox, (double)mass_weight, loss);
   return check_launch("sg_residual_loss");
 }
 

@@ -40,7 +40,7 @@ def _load():
     L.sg_adam.argtypes = [vp, vp, vp, vp, ll, i, f, f, f, f, vp, vp]
     L.sg_normalize.argtypes = [vp, i, i, ll, vp, vp, vp, vp]
     L.sg_pack.argtypes = [vp, i, i, ll, i, vp, vp]
-    L.sg_residual_loss.argtypes = [vp, vp, vp, vp, i, i, ll, i, vp, vp, vp, vp]
+    L.sg_residual_loss.argtypes = [vp, vp, vp, vp, i, i, ll, i, f, vp, vp, vp, vp]
     L.sg_unpack.argtypes = [vp, vp, vp, i, i, ll, i, vp, vp, vp, vp]
     L.sg_coarsen.argtypes = [vp, vp, vp, i, i, i, i, i, vp, vp]
     L.sg_phi_budget.argtypes = [vp, i, i, i, i, i, vp, vp]
@@ -133,13 +133,15 @@ def pack(xn, cpad, out=None, stream=None):
     return out
 
 
-def residual_loss(xn, tn, r, dr, loss=None, ws=None, rs=None, stream=None):
-    """pred = xn + rs * r; mean squared error against tn and its gradient dr."""
+def residual_loss(xn, tn, r, dr, loss=None, ws=None, rs=None, mass_weight=0.0, stream=None):
+    """pred = xn + rs * r; mean squared error against tn (+ the phase-field
+    content term weighted by mass_weight) and its gradient dr.  ws: 2048
+    doubles."""
     n, c = xn.shape[:2]
     vox = xn[0, 0].numel()
     cpad = r.shape[-1]
-    _check(lib.sg_residual_loss(_p(xn), _p(tn), _p(r), _p(rs), n, c, vox, cpad, _p(dr), _p(loss), _p(ws),
-                                _s(stream)))
+    _check(lib.sg_residual_loss(_p(xn), _p(tn), _p(r), _p(rs), n, c, vox, cpad, float(mass_weight), _p(dr),
+                                _p(loss), _p(ws), _s(stream)))
 
 
 def unpack(xn, r, shift, scale, out=None, rs=None, stream=None):

@@ -12,7 +12,7 @@ convolution) with additive skip connections from the encoder, and a linear
 output layer whose result, times a fixed increment scale, is added to the
 input (the network predicts the increment).  Weights are bf16 with float master copies; accumulation is
 FP32; Adam updates the master copies.  Training minimises the mean squared
-error of the normalised fields.
+error of the normalised fields plus a weighted phase-field content term.
 
 The fields are normalised with fixed physical scales: phi as is, velocity by
 the jet velocity, pressure by rho_H u_j^2.
@@ -26,6 +26,9 @@ from . import nn
 
 FIELDS = ("phi", "u_x", "u_y", "u_z", "p")
 CIN = 5
+# weight of the phase-field content term of the loss (mean over samples of
+# the squared mean residual of the normalised phase field)
+MASS_WEIGHT = 1.0e4
 # a prediction that violates the phase-field budget by more than this
 # (relative) is handed to the solver
 FALLBACK_THRESHOLD = 1e-3
@@ -68,7 +71,7 @@ class Network:
     """The encoder-decoder on a fixed batch shape [batch, 5, d, h, w]."""
 
     def __init__(self, batch, d, h, w, widths=(16, 32, 64), device="cuda", seed=0, lr=1e-3,
-                 u_jet=0.02, increment_scale=INCREMENT_SCALE, stream=None):
+                 u_jet=0.02, increment_scale=INCREMENT_SCALE, mass_weight=MASS_WEIGHT, stream=None):
         self.dev = torch.device(device)
         self.stream = stream
         self.batch, self.shape = batch, (d, h, w)
@@ -79,6 +82,7 @@ class Network:
         self.shift = torch.tensor(sh, device=self.dev)
         self.scale = torch.tensor(sc, device=self.dev)
         self.rs = torch.full((CIN,), float(increment_scale), dtype=torch.float32, device=self.dev)
+        self.mass_weight = float(mass_weight)
         # parameter layout: per layer W [co_p][27][ci_p] then b [co_p], one flat buffer
         self.lay = {}
         off = 0
@@ -131,7 +135,7 @@ class Network:
         self.ws = torch.empty(ws // 4 + 1, dtype=torch.float32, device=self.dev)
         d, h, w = self.shape
         self.xb = torch.empty((self.batch, d, h, w, pad16(CIN)), dtype=torch.bfloat16, device=self.dev)
-        self.loss_ws = torch.empty(1024, dtype=torch.float64, device=self.dev)
+        self.loss_ws = torch.empty(2048, dtype=torch.float64, device=self.dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=self.dev)
 
     # ---- parameters ---------------------------------------------------------
@@ -246,7 +250,7 @@ class Network:
         device scalar of the loss (before the update)."""
         r = self.forward(xn)
         nn.residual_loss(xn, tn, r, self.dz["out"], self.loss if with_loss else None, self.loss_ws,
-                         rs=self.rs, stream=self.stream)
+                         rs=self.rs, mass_weight=self.mass_weight, stream=self.stream)
         self.backward()
         self.step()
         return self.loss
@@ -254,7 +258,8 @@ class Network:
     def loss_and_grad(self, xn, tn):
         """Loss and gradients without an update (G holds the gradients)."""
         r = self.forward(xn)
-        nn.residual_loss(xn, tn, r, self.dz["out"], self.loss, self.loss_ws, rs=self.rs, stream=self.stream)
+        nn.residual_loss(xn, tn, r, self.dz["out"], self.loss, self.loss_ws, rs=self.rs,
+                         mass_weight=self.mass_weight, stream=self.stream)
         self.backward()
         return self.loss
 

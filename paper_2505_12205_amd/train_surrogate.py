@@ -158,7 +158,7 @@ def evaluate(net: SG.Network, rec: Recorder, pairs: np.ndarray, bs: int):
     pb = torch.empty_like(xb)
     zero = torch.zeros((bs,) + rec.shape[1:] + (16,), dtype=torch.bfloat16, device="cuda")
     dr = torch.empty_like(zero)
-    ws = torch.empty(1024, dtype=torch.float64, device="cuda")
+    ws = torch.empty(2048, dtype=torch.float64, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     pairs = pairs[pairs[:, 0] >= rec.nd]  # k >= 1
     mse_net, mse_per, phi_net, phi_per, drift_net, drift_lbm = [], [], [], [], [], []
@@ -204,7 +204,7 @@ def rollout(net1: SG.Network, rec: Recorder, held, k0: int, lags: int):
     t = torch.empty_like(x)
     zero = torch.zeros((1,) + rec.shape[1:] + (16,), dtype=torch.bfloat16, device="cuda")
     dr = torch.empty_like(zero)
-    ws = torch.empty(1024, dtype=torch.float64, device="cuda")
+    ws = torch.empty(2048, dtype=torch.float64, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     out = {"net": np.zeros(lags), "persistence": np.zeros(lags)}
     for d in held:
@@ -256,13 +256,16 @@ def main(argv=None):
     ap.add_argument("--train-seconds", type=float, default=360.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--weights", default="", help="start from these weights (npz)")
+    ap.add_argument("--mass-weight", type=float, default=SG.MASS_WEIGHT,
+                    help="weight of the phase-field content term of the loss")
     args = ap.parse_args(argv)
     os.makedirs(args.out, exist_ok=True)
     log(f"generating {args.snapshots} snapshots x 64 domains")
     b, cfgs, rec, t_gen = generate(args.snapshots)
     train_d, held_d, tr_pairs, ho_pairs = split(len(cfgs), args.snapshots, rec)
     log(f"data: {rec.rows} snapshots in {t_gen:.0f} s; {len(tr_pairs)} training pairs, {len(ho_pairs)} held out")
-    net = SG.Network(args.batch, *rec.shape[1:], seed=args.seed, lr=args.lr, u_jet=cfgs[0]["inlet_u"])
+    net = SG.Network(args.batch, *rec.shape[1:], seed=args.seed, lr=args.lr, u_jet=cfgs[0]["inlet_u"],
+                     mass_weight=args.mass_weight)
     if args.weights:
         net.load(args.weights)
     hist, steps, t_train = train(net, rec, tr_pairs, args.epochs, args.batch, args.seed, args.train_seconds)
@@ -287,7 +290,7 @@ def main(argv=None):
         "epoch_loss": hist, "heldout": ev, "rollout_mse": ro, "throughput": tp,
         "params": int(sum(v.size for v in net.get_params().values())),
         "domains_finite_at_end": int(rec.valid[-1].sum()),
-        "mobility": cfgs[0]["mobility"],
+        "mobility": cfgs[0]["mobility"], "mass_weight": args.mass_weight,
         "fallback_threshold": FALLBACK,
     }
     with open(os.path.join(args.out, "report.json"), "w") as f:

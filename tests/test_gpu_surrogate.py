@@ -187,8 +187,8 @@ def test_adam_matches_oracle():
     assert (pb.float().cpu().numpy() == _bf(got)).all()
 
 
-def _net_case(torch, surrogate, widths=(16, 32, 16), shape=(8, 8, 12), batch=2, seed=3, scale=1.0):
-    net = surrogate.Network(batch, *shape, widths=widths, seed=seed, increment_scale=scale)
+def _net_case(torch, surrogate, widths=(16, 32, 16), shape=(8, 8, 12), batch=2, seed=3, scale=1.0, mw=0.0):
+    net = surrogate.Network(batch, *shape, widths=widths, seed=seed, increment_scale=scale, mass_weight=mw)
     params = net.get_params()
     rng = np.random.default_rng(seed)
     for k in params:  # bf16-representable weights, non-zero biases
@@ -235,7 +235,7 @@ def test_training_lowers_the_loss():
     torch, nn, surrogate = _mods()
     rng = np.random.default_rng(11)
     batch, shape = 4, (16, 16, 16)
-    net = surrogate.Network(batch, *shape, seed=1, lr=2e-3, increment_scale=1.0)
+    net = surrogate.Network(batch, *shape, seed=1, lr=2e-3, increment_scale=1.0, mass_weight=0.0)
     # a learnable map: the target is the input advected by one cell along z
     x = rng.standard_normal((batch, 5) + shape).astype(np.float32)
     t = np.roll(x, 1, axis=2) * 0.9
@@ -250,14 +250,17 @@ def test_training_lowers_the_loss():
     assert losses[-1] < 0.6 * losses[0]
 
 
-def test_network_increment_scale():
-    """The production increment scale (0.05) enters the prediction and the
-    loss gradient: loss and the output layer's gradients against the oracle
-    with the same scale (the layers below are covered at scale 1)."""
+def test_network_increment_scale_and_mass_term():
+    """The production increment scale and phase-field content weight enter
+    the prediction, the loss and its gradient: loss and the output layer's
+    gradients against the oracle with the same settings (the layers below
+    are covered at scale 1 without the content term)."""
     torch, nn, surrogate = _mods()
-    net, params, x, t = _net_case(torch, surrogate, scale=surrogate.INCREMENT_SCALE, seed=5)
+    net, params, x, t = _net_case(torch, surrogate, scale=surrogate.INCREMENT_SCALE, seed=5,
+                                  mw=surrogate.MASS_WEIGHT)
+    t[:, 0] += 1e-3  # a phase-field content offset, so the mass term matters
     spec = S.layers(5, *(16, 32, 16))
-    Lo, Go = S.loss_and_grad(params, spec, x, t, surrogate.INCREMENT_SCALE)
+    Lo, Go = S.loss_and_grad(params, spec, x, t, surrogate.INCREMENT_SCALE, surrogate.MASS_WEIGHT)
     xn = torch.tensor(x, dtype=torch.float32, device="cuda")
     tn = torch.tensor(t, dtype=torch.float32, device="cuda")
     _log("[gpu] network increment scale")

@@ -157,3 +157,24 @@ def test_pool2_and_mass_drift():
     a = np.ones((2, 3, 3))
     b = a * 1.001
     assert np.allclose(S.relative_mass_drift(b, a), 1e-3)
+
+
+def test_mass_term_gradient_and_value():
+    rng = np.random.default_rng(21)
+    pred = rng.standard_normal((3, 5, 4, 3, 2))
+    tgt = rng.standard_normal((3, 5, 4, 3, 2))
+    mw = 7.0
+    L, g = S.mse(pred, tgt, mw)
+    d = pred - tgt
+    m = d[:, 0].reshape(3, -1).mean(axis=1)
+    assert abs(L - (np.mean(d * d) + mw * np.mean(m * m))) < 1e-14
+    h = 1e-6
+    for idx in [(0, 0, 1, 2, 1), (2, 0, 3, 0, 0), (1, 3, 2, 1, 1)]:
+        e = np.zeros_like(pred)
+        e[idx] = h
+        fd = (S.mse(pred + e, tgt, mw)[0] - S.mse(pred - e, tgt, mw)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-8
+    # a uniform shift of the phase field in one sample is penalised beyond the plain MSE
+    shifted = tgt.copy()
+    shifted[0, 0] += 0.01
+    assert S.mse(shifted, tgt, mw)[0] > S.mse(shifted, tgt, 0.0)[0]
