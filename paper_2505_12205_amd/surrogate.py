@@ -28,7 +28,7 @@ FIELDS = ("phi", "u_x", "u_y", "u_z", "p")
 CIN = 5
 # weight of the phase-field content term of the loss (mean over samples of
 # the squared mean residual of the normalised phase field)
-MASS_WEIGHT = 1.0e4
+MASS_WEIGHT = 2.0e3
 # a prediction that violates the phase-field budget by more than this
 # (relative) is handed to the solver
 FALLBACK_THRESHOLD = 1e-3
