@@ -17,6 +17,10 @@
    fallback threshold (those samples are advanced by the solver instead);
    rollouts of several lags from one snapshot; throughput of the network
    against the solver for the same advance.
+4. Regimes: each domain's median intact length over the last 50 snapshots,
+   from the solver and from a 50-lag network rollout, classifies it as
+   dripping or jetting (more than two nozzle diameters); each proposes the
+   critical Weber number of the transition.
 Writes DIR/jet_surrogate.npz (weights) and DIR/report.json; progress goes to
 stdout.  Every arithmetic step runs in the library kernels (liblbm.so and
 libsurr.so); torch holds the buffers and computes the report's summary
@@ -222,6 +226,78 @@ def rollout(net1: SG.Network, rec: Recorder, held, k0: int, lags: int):
     return {k: v.tolist() for k, v in out.items()}
 
 
+def intact_length(phi: np.ndarray) -> np.ndarray:
+    """Intact length in fine lattice units of coarse phase fields [n, d, h, w]:
+    the planes from the inlet that hold liquid (phi > 1/2) without a gap,
+    times 2 (a coarse plane spans two fine planes)."""
+    has = (phi > 0.5).reshape(phi.shape[0], phi.shape[1], -1).any(axis=2)
+    run = np.where(has.all(axis=1), phi.shape[1], np.argmin(has, axis=1))
+    return 2 * run
+
+
+def critical_weber(we: np.ndarray, jetting: np.ndarray) -> float:
+    """The Weber number that best splits dripping (below) from jetting
+    (above): the split with the fewest misclassified domains, placed at the
+    geometric mean of its two neighbours."""
+    o = np.argsort(we)
+    w, j = we[o], jetting[o].astype(int)
+    best, cut = None, 0
+    for i in range(len(w) + 1):
+        err = j[:i].sum() + (1 - j[i:]).sum()
+        if best is None or err < best:
+            best, cut = err, i
+    if cut == 0:
+        return float(w[0])
+    if cut == len(w):
+        return float(w[-1])
+    return float(np.sqrt(w[cut - 1] * w[cut]))
+
+
+def regime_study(net: SG.Network, rec: Recorder, cfgs, k_from: int, k_to: int, held):
+    """Dripping / jetting per domain (median intact length over snapshots
+    k_from..k_to above 2 nozzle diameters = jetting) from the solver's
+    snapshots and from network rollouts started at snapshot k_from - 1, and
+    the critical Weber number each proposes."""
+    We = np.array(W.sweep_weber(len(cfgs)))
+    D = 2.0 * cfgs[0]["inlet_radius"]
+    ok = np.array([rec.valid[k_to, d] for d in range(rec.nd)])
+    ks = list(range(k_from, k_to + 1))
+    lb_lbm = np.zeros((rec.nd, len(ks)))
+    lb_net = np.zeros((rec.nd, len(ks)))
+    bs = net.batch
+    x = torch.empty((bs,) + rec.shape, dtype=torch.float32, device="cuda")
+    one = torch.ones(5, device="cuda")
+    zero5 = torch.zeros(5, device="cuda")
+    for d0 in range(0, rec.nd, bs):
+        doms = list(range(d0, min(d0 + bs, rec.nd)))
+        pad = doms + [doms[-1]] * (bs - len(doms))
+        nn.gather(rec.store, torch.tensor([rec.row(d, k_from - 1) for d in pad], device="cuda"), x)
+        for j, k in enumerate(ks):
+            r = net.forward(x)
+            x = nn.unpack(x, r, zero5, one, rs=net.rs)  # next normalised state
+            phi_net = x[:len(doms), 0].cpu().numpy()  # phi is normalised by 1
+            lb_net[doms, j] = intact_length(phi_net)
+            phi_lbm = rec.store[[rec.row(d, k) for d in doms], 0].cpu().numpy()
+            lb_lbm[doms, j] = intact_length(phi_lbm)
+    med_lbm = np.median(lb_lbm, axis=1)
+    med_net = np.median(lb_net, axis=1)
+    jet_lbm = med_lbm / D > 2.0
+    jet_net = med_net / D > 2.0
+    hmask = np.zeros(rec.nd, bool)
+    hmask[held] = True
+    return {
+        "snapshots": [k_from, k_to], "solver_step_range": [k_from * LAG, k_to * LAG],
+        "criterion": "median intact length over the snapshots > 2 nozzle diameters",
+        "weber": We.tolist(), "finite": ok.tolist(),
+        "intact_length_solver": med_lbm.tolist(), "intact_length_network_rollout": med_net.tolist(),
+        "jetting_solver": jet_lbm.tolist(), "jetting_network_rollout": jet_net.tolist(),
+        "regime_agreement": float(np.mean(jet_lbm[ok] == jet_net[ok])),
+        "regime_agreement_heldout": float(np.mean(jet_lbm[ok & hmask] == jet_net[ok & hmask])),
+        "we_critical_solver": critical_weber(We[ok], jet_lbm[ok]),
+        "we_critical_network": critical_weber(We[ok], jet_net[ok]),
+    }
+
+
 def throughput(net: SG.Network, rec: Recorder, b: lbm.Batch, held, reps: int = 5):
     """Seconds per 32-step advance of the held-out domains: the network on
     the coarse windows (batch = number of held-out domains) and the solver
@@ -281,13 +357,18 @@ def main(argv=None):
     log(f"rollout: {ro}")
     tp = throughput(SG.Network(len(held_d), *rec.shape[1:], u_jet=cfgs[0]["inlet_u"]), rec, b, held_d)
     log(f"throughput: {tp}")
+    k_to = args.snapshots - 1
+    k_from = max(1, k_to - 49)
+    rg = regime_study(net, rec, cfgs, k_from, k_to, held_d)
+    log(f"regimes: We_cr solver {rg['we_critical_solver']:.3f}, network {rg['we_critical_network']:.3f}; "
+        f"agreement {rg['regime_agreement']:.3f} (held out {rg['regime_agreement_heldout']:.3f})")
     We = W.sweep_weber()
     report = {
         "domains": len(cfgs), "snapshots_per_domain": args.snapshots, "lag_steps": LAG,
         "window": list(rec.shape), "data_seconds": t_gen, "train_pairs": int(len(tr_pairs)),
         "heldout_pairs": int(len(ho_pairs)), "heldout_weber": [float(We[d]) for d in held_d],
         "batch": args.batch, "lr": args.lr, "train_steps": steps, "train_seconds": t_train,
-        "epoch_loss": hist, "heldout": ev, "rollout_mse": ro, "throughput": tp,
+        "epoch_loss": hist, "heldout": ev, "rollout_mse": ro, "throughput": tp, "regimes": rg,
         "params": int(sum(v.size for v in net.get_params().values())),
         "domains_finite_at_end": int(rec.valid[-1].sum()),
         "mobility": cfgs[0]["mobility"], "mass_weight": args.mass_weight,
