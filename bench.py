@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
     ap.add_argument("--blocks-per-cu", type=int, default=8, help="batched launch with --tile")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only time the surrogate's training step (for profiling it alone)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
@@ -209,6 +211,9 @@ def main():
     copy_gbs = copy_probe()
     print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.copy_probe_only:
+        return
+    if args.surrogate_only:
+        print(json.dumps({"surrogate_bf16_mfma": run_surrogate(steps=args.steps)}), flush=True)
         return
     if args.batch_only:
         launch = (tile[0], tile[1], args.blocks_per_cu, False) if tile else None
