@@ -256,6 +256,25 @@ constexpr int kAllTapsMaxTiles = 2;  // larger (co, ci) take one tap per block
 constexpr int WV = 64;       // voxels per LDS tile
 constexpr int WP = WV + 8;   // padded LDS row (bf16 elements)
 
+// Transposed LDS store of a 64-voxel tile, two voxels per 32-bit word: lane
+// v holds channels c4..c4+3 of voxel v; lanes 2i and 2i+1 swap halves (DPP)
+// so that the even lane writes channels c4 and c4+2, the odd lane c4+1 and
+// c4+3, each as (voxel 2i, voxel 2i+1).  t[c * WP + v] in bf16 elements.
+__device__ __forceinline__ void pair_store4(uint16_t* t, int c4, int lane, v4s val) {
+  const uint32_t d0 = (uint32_t)(uint16_t)val[0] | ((uint32_t)(uint16_t)val[1] << 16);
+  const uint32_t d1 = (uint32_t)(uint16_t)val[2] | ((uint32_t)(uint16_t)val[3] << 16);
+  // quad_perm(1, 0, 3, 2): the value of lane ^ 1
+  const uint32_t e0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d0, 0xB1, 0xF, 0xF, false);
+  const uint32_t e1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)d1, 0xB1, 0xF, 0xF, false);
+  const bool odd = lane & 1;
+  const uint32_t w0 = odd ? ((e0 >> 16) | (d0 & 0xFFFF0000u)) : ((d0 & 0xFFFFu) | (e0 << 16));
+  const uint32_t w1 = odd ? ((e1 >> 16) | (d1 & 0xFFFF0000u)) : ((d1 & 0xFFFFu) | (e1 << 16));
+  const int c = c4 + (odd ? 1 : 0);
+  uint32_t* t32 = (uint32_t*)t;
+  t32[c * (WP / 2) + (lane >> 1)] = w0;
+  t32[(c + 2) * (WP / 2) + (lane >> 1)] = w1;
+}
+
 // Each wave takes one 16-voxel slice of every 64-voxel tile for all
 // (CO/16) x (CI/16) output tiles; the four waves' sums are added through LDS
 // at the end.  Tap-0 blocks also sum dz (the bias gradient) with an MFMA
@@ -284,33 +303,31 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
   for (long long vt = v0; vt < v1; vt += WV) {
     __syncthreads();
+    // lane = voxel of the tile; the waves split the channel groups
+    const long long vv0 = vt + lane;
+    const bool vok = vv0 < v1;
     // dz tile, transposed: dzT[o][voxel]
-    for (int i = threadIdx.x; i < WV * (CO / 4); i += 256) {
-      const int vl = i / (CO / 4), c4 = (i % (CO / 4)) * 4;
-      const long long v = vt + vl;
-      v4s val = {0, 0, 0, 0};
-      if (v < v1) val = ld4(dz + v * CO + c4);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) dzT[(c4 + j) * WP + vl] = (uint16_t)val[j];
+    for (int c4 = wv * 4; c4 < CO; c4 += 16) {
+      const v4s val = vok ? ld4(dz + vv0 * CO + c4) : (v4s){0, 0, 0, 0};
+      pair_store4(dzT, c4, lane, val);
     }
     // gathered input of this tap, transposed: xT[c][voxel]
-    for (int i = threadIdx.x; i < WV * (CI / 4); i += 256) {
-      const int vl = i / (CI / 4), c4 = (i % (CI / 4)) * 4;
-      long long v = vt + vl;
-      v4s val = {0, 0, 0, 0};
-      if (v < v1) {
-        const int px = (int)(v % g.ow);
-        v /= g.ow;
-        const int py = (int)(v % g.oh);
-        v /= g.oh;
-        const int pz = (int)(v % g.od);
-        const int n = (int)(v / g.od);
-        const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
-        if (qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU)
-          val = ld4(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * CI + c4);
+    {
+      long long v = vok ? vv0 : v0;
+      const int px = (int)(v % g.ow);
+      v /= g.ow;
+      const int py = (int)(v % g.oh);
+      v /= g.oh;
+      const int pz = (int)(v % g.od);
+      const int n = (int)(v / g.od);
+      const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
+      const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+      const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
+                                 (in ? qx / U : 0)) * CI;
+      for (int c4 = wv * 4; c4 < CI; c4 += 16) {
+        const v4s val = in ? ld4(src + c4) : (v4s){0, 0, 0, 0};
+        pair_store4(xT, c4, lane, val);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xT[(c4 + j) * WP + vl] = (uint16_t)val[j];
     }
     __syncthreads();
     const int kofs = wv * 16 + 4 * quad;  // this wave's voxel slice
