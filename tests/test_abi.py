@@ -86,3 +86,41 @@ def test_surrogate_rejects_bad_sizes_on_host():
     assert nn.lib.sg_conv3d_fwd(None, 1, 4, 4, 4, 16, None, None, 16, 2, 2, 1, None, None, None, None) == -1
     assert nn.lib.sg_conv3d_bwd_weight_workspace(1, 4, 4, 4, 16, 16, 2, 2) == 0
     assert nn.lib.sg_conv3d_bwd_weight_workspace(2, 8, 8, 8, 16, 32, 2, 1) > 0
+
+
+def test_batch_layout_and_validation_on_host():
+    """lbm_batch_state_bytes: the sum of the domains' 256-byte aligned
+    layouts; batches of mixed lattice or storage, and empty ones, are
+    rejected before any device call."""
+    from paper_2505_12205_amd import lbm
+    from paper_2505_12205_amd import workloads as W
+    doms = [W.jet3d(nx=16, ny=16, nz=nz, radius=4.0) for nz in (24, 40)]
+    arr = (lbm.Params * 2)(*[lbm.make_params(d[0], "fp16") for d in doms])
+    n = C.c_size_t()
+    assert lbm.lib.lbm_batch_state_bytes(2, arr, C.byref(n)) == 0
+    each = [lbm.state_bytes(d[0], "fp16") for d in doms]
+    assert n.value >= sum(each) and n.value <= sum(each) + 2 * 256
+    mixed = (lbm.Params * 2)(lbm.make_params(doms[0][0], "fp16"), lbm.make_params(doms[1][0], "fp32"))
+    assert lbm.lib.lbm_batch_state_bytes(2, mixed, C.byref(n)) == -1
+    d2, _, _ = W.drop2d(n=16)
+    mixed = (lbm.Params * 2)(lbm.make_params(doms[0][0], "fp32"), lbm.make_params(d2, "fp32"))
+    assert lbm.lib.lbm_batch_state_bytes(2, mixed, C.byref(n)) == -1
+    assert lbm.lib.lbm_batch_state_bytes(0, arr, C.byref(n)) == -1
+
+
+def test_regime_helpers():
+    """Intact length of coarse phase fields and the critical Weber split."""
+    import numpy as np
+
+    from paper_2505_12205_amd.train_surrogate import critical_weber, intact_length
+    phi = np.zeros((3, 10, 3, 3))
+    phi[0, :4, 1, 1] = 1.0     # 4 planes, then a gap, then a detached drop
+    phi[0, 6:8, 1, 1] = 1.0
+    phi[1, :, 0, 0] = 0.9      # liquid through the whole window
+    phi[2, 0, 1, 1] = 0.4      # below the threshold: no liquid
+    assert list(intact_length(phi)) == [8, 20, 0]   # fine units: 2 per coarse plane
+    we = np.array([0.5, 1.0, 2.0, 4.0, 8.0])
+    assert abs(critical_weber(we, np.array([0, 0, 1, 1, 1])) - np.sqrt(2.0)) < 1e-12
+    assert critical_weber(we, np.array([1, 1, 1, 1, 1])) == 0.5
+    # one outlier: the split with the fewest misclassified domains
+    assert abs(critical_weber(we, np.array([0, 1, 0, 1, 1])) - np.sqrt(0.5)) < 1e-12

@@ -265,3 +265,28 @@ def test_zero_steps_and_tiny_domain():
     phi_g, u_g, _ = s.fields()
     phi_o, u_o, _ = o.fields()
     assert np.abs(phi_g.cpu().numpy() - phi_o).max() < 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_rest_and_uniform_flow_are_fixed_points(storage):
+    """Degenerate states: a single phase at rest stays exactly at rest, and
+    a uniform flow through a periodic box keeps its velocity (both are fixed
+    points of the step: no gradients, equilibrium populations)."""
+    lbm = _lbm()
+    cfg, _, _ = W.rt3d(nx=16, ny=20, nz=8, lref=256)
+    cfg = dict(cfg, bc=("periodic",) * 6, gravity=(0.0, 0.0, 0.0))
+    shape = (8, 20, 16)
+    for phi_value in (1.0, 0.0):
+        phi0 = np.full(shape, phi_value)
+        s = lbm.Sim(cfg, phi0, None, storage=storage).step(50)
+        phi, u, _ = s.fields()
+        _log(f"[gpu] rest {storage} phi={phi_value}: max|u|={u.abs().max().item():.2e}")
+        assert u.abs().max().item() == 0.0
+        assert (phi - phi_value).abs().max().item() <= 1e-6
+    u0 = np.zeros((3,) + shape)
+    u0[0], u0[1], u0[2] = 0.01, -0.005, 0.002
+    s = lbm.Sim(cfg, np.ones(shape), u0, storage=storage).step(50)
+    phi, u, _ = s.fields()
+    du = np.abs(u.cpu().numpy() - u0).max()
+    _log(f"[gpu] uniform flow {storage}: max|u-u0|={du:.2e}")
+    assert du <= (1e-6 if storage == "fp32" else 2e-5)
