@@ -15,8 +15,9 @@
  *     frees every buffer; nothing is allocated by these calls;
  *   - activations are bf16 (stored as uint16_t) in N, D, H, W, C order with C
  *     a multiple of 16 (at most 64); weights are bf16 [co][27][ci] (tap
- *     index k = (kz * 3 + ky) * 3 + kx) with the transposed copy [27][ci][co]
- *     used by the data gradient; master weights, gradients and optimiser
+ *     index k = (kz * 3 + ky) * 3 + kx) with the flipped copy
+ *     wf[c][26 - k][o] = w[o][k][c] used by the data gradient; master
+ *     weights, gradients and optimiser
  *     moments are float;
  *   - calls are asynchronous on `stream` (hipStream_t, NULL = default);
  *   - return 0 on success, SG_EINVAL for inconsistent sizes or a null
@@ -43,20 +44,23 @@ const char* sg_last_error(void);
  *   skip : nullable [n, od, oh, ow, co], added after the activation;
  *   yr   : nullable, receives max(z, 0) (or z) before the skip is added
  *          (the gradient needs the activation's own sign).
- * stride 2 with up 2 is rejected. */
+ * stride 2 with up 2 is rejected.  Stride-1 layers with ci == co <= 32
+ * stage each block's input brick with its halo in LDS. */
 int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* wgt,
                   const float* bias, int co, int stride, int up, int relu, const uint16_t* skip,
                   uint16_t* y, uint16_t* yr, void* stream);
 
 /* Data gradient.  dz [n, od, oh, ow, co] (gradient of the layer's
- * pre-activation); wgt_t [27][ci][co]; output at the layer input
- * [n, d, h, w, ci]:
+ * pre-activation); wgt_f [ci][27][co], the flipped copy of the layer's
+ * weights (sg_flip_weights); output at the layer input [n, d, h, w, ci]:
  *   g    = sum over the taps and output voxels that read each input voxel
  *          (+ add[...] if add is non-null: a gradient arriving by another path);
  *   da   : nullable, receives g;
  *   dzp  : receives g masked by mask > 0 (mask: the previous layer's
- *          activation before any skip; null: no mask). */
-int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wgt_t,
+ *          activation before any skip; null: no mask).
+ * Stride-1 layers with ci == co == 16 run as a convolution of dz with
+ * wgt_f from an LDS halo tile. */
+int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wgt_f,
                        int co, int stride, int up, const uint16_t* add, const uint16_t* mask,
                        uint16_t* da, uint16_t* dzp, void* stream);
 
@@ -71,8 +75,8 @@ size_t sg_conv3d_bwd_weight_workspace(int n, int d, int h, int w, int ci, int co
 int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* dz, int co,
                          int stride, int up, void* ws, size_t ws_bytes, float* dw, float* db, void* stream);
 
-/* Transposed bf16 weight copy: wt[k][c][o] = w[o][k][c]. */
-int sg_transpose_weights(const uint16_t* w, int co, int ci, uint16_t* wt, void* stream);
+/* Flipped bf16 weight copy for the data gradient: wf[c][26 - k][o] = w[o][k][c]. */
+int sg_flip_weights(const uint16_t* w, int co, int ci, uint16_t* wf, void* stream);
 
 /* Adam step with bias correction over a flat float buffer of `count`
  * parameters (master p, moments m and v, gradient g), step number t >= 1;

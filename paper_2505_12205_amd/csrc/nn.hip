@@ -164,11 +164,120 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 }
 
 // ---------------------------------------------------------------------------
+// stride-1 convolution from an LDS halo tile (C channels in and out)
+// ---------------------------------------------------------------------------
+// A block owns TZ x TY rows of 16 voxels along x; it stages the input brick
+// with a one-voxel halo in LDS once, and every tap reads a shifted window of
+// it.  MODE 0 is the forward epilogue (bias, relu, the activation before the
+// skip in y2, skip add); MODE 1 is the data gradient of a stride-1 layer:
+// with the flipped weights wf[c][26 - k][o] = w[o][k][c] the gradient is the
+// same convolution of dz, and the epilogue adds `add`, stores the sum in y2
+// and the sum masked by mask > 0 in y.
+template <int C>
+struct HaloTile {
+  static constexpr int NS = C / 16, MS = 8 / NS, ROWS = 4 * MS;
+  static constexpr int TY = ROWS >= 16 ? 8 : 4, TZ = ROWS / TY;
+  static constexpr int HX = 18, HY = TY + 2, HZ = TZ + 2;
+  static constexpr int ELEMS = HZ * HY * HX * C;
+};
+
+struct HGeo {
+  int n, d, h, w;          // extent (input = output)
+  int ntx, nty, ntz;       // tiles along x, y, z
+};
+
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ x, const uint16_t* __restrict__ wgt,
+                                                   const float* __restrict__ bias,
+                                                   const uint16_t* __restrict__ other,
+                                                   const uint16_t* __restrict__ mask, uint16_t* __restrict__ y,
+                                                   uint16_t* __restrict__ y2, HGeo g, int relu) {
+  using T = HaloTile<C>;
+  constexpr int NS = T::NS, MS = T::MS, TY = T::TY, TZ = T::TZ, HX = T::HX, HY = T::HY, HZ = T::HZ;
+  __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS];
+  int b = blockIdx.x;
+  const int tx = b % g.ntx;
+  b /= g.ntx;
+  const int ty = b % g.nty;
+  b /= g.nty;
+  const int tz = b % g.ntz;
+  const int n = b / g.ntz;
+  const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
+  // stage the brick and its halo, zero outside the grid
+  for (int i = threadIdx.x; i < HZ * HY * HX * (C / 8); i += 256) {
+    const int c8 = (i % (C / 8)) * 8, vox = i / (C / 8);
+    const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    v8bf val = {};
+    if (gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
+      val = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * C + c8);
+    *(v8bf*)&halo[vox * C + c8] = val;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  v4f acc[MS][NS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+  constexpr int K = 27 * C;
+  constexpr int csh = NS == 1 ? 4 : (NS == 2 ? 5 : 6);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + 8 * quad;  // K is a multiple of 32 for C >= 32, and of 16 for C = 16
+    const bool kin = k < K;
+    const int tap = kin ? (k >> csh) : 0, c = k - (tap << csh);
+    const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+    v8bf a[MS], bb[NS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      const int r = wv * MS + m, rz = r / TY, ry = r % TY;
+      a[m] = kin ? *(const v8bf*)&halo[(((rz + kz) * HY + (ry + ky)) * HX + (col + kx)) * C + c] : (v8bf){};
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : (v8bf){};
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
+  }
+  // lane holds D[4 quad + r][col]: voxel x0 + 4 quad + r of row m, channel s*16 + col
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    const int rr = wv * MS + m, gz = z0 + rr / TY, gy = y0 + rr % TY;
+    if (gz >= g.d || gy >= g.h) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gx = x0 + 4 * quad + r;
+      if (gx >= g.w) continue;
+      const long long v = (((long long)n * g.d + gz) * g.h + gy) * g.w + gx;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int o = s * 16 + col;
+        const long long i = v * C + o;
+        float val = acc[m][s][r];
+        if (MODE == 0) {
+          val += bias[o];
+          if (relu) val = fmaxf(val, 0.0f);
+          if (y2) y2[i] = f2bf(val);
+          if (other) val += bf2f(other[i]);
+        } else {
+          if (other) val += bf2f(other[i]);
+          if (y2) y2[i] = f2bf(val);
+          if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
+        }
+        y[i] = f2bf(val);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // data gradient: g[r, c] = sum over (k, p) with src(p, k) = r of w[o,k,c] dz[p, o]
 // ---------------------------------------------------------------------------
 template <int CI, int S, int U>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restrict__ dz,
-                                                       const uint16_t* __restrict__ wt, Geo g,
+                                                       const uint16_t* __restrict__ wf, Geo g,
                                                        const uint16_t* __restrict__ add,
                                                        const uint16_t* __restrict__ mask,
                                                        uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
@@ -219,7 +328,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
       a[m] = v ? ld8(dz + ((((long long)nb[m] * g.od + ppz) * g.oh + ppy) * g.ow + ppx) * g.co + o) : zero;
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) b[s] = kin ? ld8(wt + ((long long)tap * CI + s * 16 + col) * g.co + o) : zero;
+    for (int s = 0; s < NS; ++s)
+      b[s] = kin ? ld8(wf + ((long long)(s * 16 + col) * 27 + (26 - tap)) * g.co + o) : zero;
   };
   for (int k0 = 0; k0 < K; k0 += 32) {
     v8bf a[MS], b[NS];
@@ -525,11 +635,11 @@ __global__ __launch_bounds__(256) void k_bwd_w_reduce(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
-__global__ void k_transpose_w(const uint16_t* __restrict__ w, int co, int ci, uint16_t* __restrict__ wt) {
+__global__ void k_flip_w(const uint16_t* __restrict__ w, int co, int ci, uint16_t* __restrict__ wf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [o][k][c]
   if (i >= co * 27 * ci) return;
   const int c = i % ci, k = (i / ci) % 27, o = i / (ci * 27);
-  wt[((long long)k * ci + c) * co + o] = w[i];
+  wf[((long long)c * 27 + (26 - k)) * co + o] = w[i];
 }
 
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
@@ -772,6 +882,36 @@ void launch_bwd_w_su(const Geo& g, const uint16_t* x, const uint16_t* dz, int nc
   else launch_bwd_w_co<64, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
 }
 
+template <int C, int MODE>
+void launch_halo_c(int n, int d, int h, int w, const uint16_t* x, const uint16_t* wgt, const float* bias,
+                   const uint16_t* other, const uint16_t* mask, uint16_t* y, uint16_t* y2, int relu, hipStream_t st) {
+  using T = HaloTile<C>;
+  HGeo g;
+  g.n = n;
+  g.d = d;
+  g.h = h;
+  g.w = w;
+  g.ntx = (w + 15) / 16;
+  g.nty = (h + T::TY - 1) / T::TY;
+  g.ntz = (d + T::TZ - 1) / T::TZ;
+  const long long blocks = (long long)g.ntx * g.nty * g.ntz * n;
+  hipLaunchKernelGGL((k_conv_halo<C, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, x, wgt, bias, other, mask, y,
+                     y2, g, relu);
+}
+
+// The halo tile pays where the layer is narrow: at 64 channels a block holds
+// only 8 rows and stages 3.4x its own voxels, and the direct kernel is faster
+// (measured per layer width; the data gradient gains at 16 channels only).
+bool halo_fwd(int c) { return c <= 32; }
+bool halo_data(int c) { return c == 16; }
+
+template <int MODE>
+void launch_halo(int n, int d, int h, int w, int c, const uint16_t* x, const uint16_t* wgt, const float* bias,
+                 const uint16_t* other, const uint16_t* mask, uint16_t* y, uint16_t* y2, int relu, hipStream_t st) {
+  if (c == 16) launch_halo_c<16, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
+  else launch_halo_c<32, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
+}
+
 // voxel chunking of the weight gradient: about 2048 blocks (the per-tap
 // kernel has 27 blocks per chunk, the all-taps kernel one)
 void wchunks(const Geo& g, int& nchunk, long long& vchunk) {
@@ -807,23 +947,31 @@ int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const u
   if (!x || !wgt || !bias || !y) return fail(SG_EINVAL, "null tensor");
   const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
   hipStream_t st = (hipStream_t)stream;
+  if (stride == 1 && up == 1 && ci == co && halo_fwd(co)) {
+    launch_halo<0>(n, d, h, w, co, x, wgt, bias, skip, nullptr, y, yr, relu, st);
+    return check_launch("sg_conv3d_fwd");
+  }
   if (stride == 1 && up == 1) launch_fwd_su<1, 1>(g, x, wgt, bias, skip, y, yr, relu, st);
   else if (stride == 2) launch_fwd_su<2, 1>(g, x, wgt, bias, skip, y, yr, relu, st);
   else launch_fwd_su<1, 2>(g, x, wgt, bias, skip, y, yr, relu, st);
   return check_launch("sg_conv3d_fwd");
 }
 
-int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wgt_t, int co,
+int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wgt_f, int co,
                        int stride, int up, const uint16_t* add, const uint16_t* mask, uint16_t* da, uint16_t* dzp,
                        void* stream) {
   int rc = check_conv(n, d, h, w, ci, co, stride, up);
   if (rc) return rc;
-  if (!dz || !wgt_t || !dzp) return fail(SG_EINVAL, "null tensor");
+  if (!dz || !wgt_f || !dzp) return fail(SG_EINVAL, "null tensor");
   const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
   hipStream_t st = (hipStream_t)stream;
-  if (stride == 1 && up == 1) launch_bwd_data_su<1, 1>(g, dz, wgt_t, add, mask, da, dzp, st);
-  else if (stride == 2) launch_bwd_data_su<2, 1>(g, dz, wgt_t, add, mask, da, dzp, st);
-  else launch_bwd_data_su<1, 2>(g, dz, wgt_t, add, mask, da, dzp, st);
+  if (stride == 1 && up == 1 && ci == co && halo_data(ci)) {
+    launch_halo<1>(n, d, h, w, ci, dz, wgt_f, nullptr, add, mask, dzp, da, 0, st);
+    return check_launch("sg_conv3d_bwd_data");
+  }
+  if (stride == 1 && up == 1) launch_bwd_data_su<1, 1>(g, dz, wgt_f, add, mask, da, dzp, st);
+  else if (stride == 2) launch_bwd_data_su<2, 1>(g, dz, wgt_f, add, mask, da, dzp, st);
+  else launch_bwd_data_su<1, 2>(g, dz, wgt_f, add, mask, da, dzp, st);
   return check_launch("sg_conv3d_bwd_data");
 }
 
@@ -859,11 +1007,11 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
   return check_launch("sg_conv3d_bwd_weight");
 }
 
-int sg_transpose_weights(const uint16_t* w, int co, int ci, uint16_t* wt, void* stream) {
-  if (!w || !wt || !chan_ok(co) || !chan_ok(ci)) return fail(SG_EINVAL, "bad weights");
+int sg_flip_weights(const uint16_t* w, int co, int ci, uint16_t* wf, void* stream) {
+  if (!w || !wf || !chan_ok(co) || !chan_ok(ci)) return fail(SG_EINVAL, "bad weights");
   const int n = co * 27 * ci;
-  hipLaunchKernelGGL(k_transpose_w, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, co, ci, wt);
-  return check_launch("sg_transpose_weights");
+  hipLaunchKernelGGL(k_flip_w, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, co, ci, wf);
+  return check_launch("sg_flip_weights");
 }
 
 int sg_adam(float* p, float* m, float* v, const float* g, long long count, int t, float lr, float beta1,

@@ -36,7 +36,7 @@ def _load():
     L.sg_conv3d_bwd_weight_workspace.argtypes = [i, i, i, i, i, i, i, i]
     L.sg_conv3d_bwd_weight_workspace.restype = sz
     L.sg_conv3d_bwd_weight.argtypes = [vp, i, i, i, i, i, vp, i, i, i, vp, sz, vp, vp, vp]
-    L.sg_transpose_weights.argtypes = [vp, i, i, vp, vp]
+    L.sg_flip_weights.argtypes = [vp, i, i, vp, vp]
     L.sg_adam.argtypes = [vp, vp, vp, vp, ll, i, f, f, f, f, vp, vp]
     L.sg_normalize.argtypes = [vp, i, i, ll, vp, vp, vp, vp]
     L.sg_pack.argtypes = [vp, i, i, ll, i, vp, vp]
@@ -51,7 +51,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("sg_last_error", "sg_conv3d_fwd", "sg_conv3d_bwd_data", "sg_conv3d_bwd_weight_workspace",
-            "sg_conv3d_bwd_weight", "sg_transpose_weights", "sg_adam", "sg_normalize", "sg_pack",
+            "sg_conv3d_bwd_weight", "sg_flip_weights", "sg_adam", "sg_normalize", "sg_pack",
             "sg_residual_loss", "sg_unpack", "sg_coarsen", "sg_phi_budget", "sg_gather")
 
 
@@ -84,12 +84,12 @@ def conv3d_fwd(x, w, b, co, stride=1, up=1, relu=True, skip=None, y=None, yr=Non
     return y
 
 
-def conv3d_bwd_data(dz, wt, n, d, h, w, ci, stride=1, up=1, add=None, mask=None, da=None, dzp=None, stream=None):
-    """dz [n, od, oh, ow, co] bf16, wt [27, ci, co] bf16 -> dzp [n, d, h, w, ci]."""
+def conv3d_bwd_data(dz, wf, n, d, h, w, ci, stride=1, up=1, add=None, mask=None, da=None, dzp=None, stream=None):
+    """dz [n, od, oh, ow, co] bf16, wf [ci, 27, co] bf16 (flip_weights) -> dzp [n, d, h, w, ci]."""
     co = _bf(dz).shape[-1]
     if dzp is None:
         dzp = torch.empty((n, d, h, w, ci), dtype=torch.bfloat16, device=dz.device)
-    _check(lib.sg_conv3d_bwd_data(_p(dz), n, d, h, w, ci, _p(_bf(wt)), co, stride, up, _p(add), _p(mask), _p(da),
+    _check(lib.sg_conv3d_bwd_data(_p(dz), n, d, h, w, ci, _p(_bf(wf)), co, stride, up, _p(add), _p(mask), _p(da),
                                   _p(dzp), _s(stream)))
     return dzp
 
@@ -105,8 +105,9 @@ def conv3d_bwd_weight(x, dz, stride, up, ws, dw, db, stream=None):
                                     ws.numel() * ws.element_size(), _p(dw), _p(db), _s(stream)))
 
 
-def transpose_weights(w, co, ci, wt, stream=None):
-    _check(lib.sg_transpose_weights(_p(_bf(w)), co, ci, _p(wt), _s(stream)))
+def flip_weights(w, co, ci, wf, stream=None):
+    """wf[c][26 - k][o] = w[o][k][c] (the data gradient's weights)."""
+    _check(lib.sg_flip_weights(_p(_bf(w)), co, ci, _p(wf), _s(stream)))
 
 
 def adam(p, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, pb=None, stream=None):

@@ -108,7 +108,7 @@ class Network:
         self.V = torch.zeros(off, **f32)
         self.G = torch.zeros(off, **f32)
         self.Pb = torch.zeros(off, dtype=torch.bfloat16, device=self.dev)
-        self.WT = {}
+        self.WF = {}
         self._alloc()
         self.init_params(seed)
 
@@ -124,7 +124,7 @@ class Network:
         sources = {L["skip"] for L in self.lay.values() if L["skip"]}
         for (name, *_r) in self.spec:
             L = self.lay[name]
-            self.WT[name] = torch.empty((27, L["cip"], L["cop"]), dtype=torch.bfloat16, device=self.dev)
+            self.WF[name] = torch.empty((L["cip"], 27, L["cop"]), dtype=torch.bfloat16, device=self.dev)
             self.y[name] = self._act(name)
             if L["skip"]:
                 self.yr[name] = self._act(name)
@@ -180,12 +180,12 @@ class Network:
         # step with zero moments copies the master weights exactly
         zero = torch.zeros_like(self.P)
         nn.adam(self.P, zero.clone(), zero.clone(), zero, 1, 0.0, pb=self.Pb, stream=self.stream)
-        self._transpose()
+        self._flip()
 
-    def _transpose(self):
+    def _flip(self):
         for (name, *_r) in self.spec:
             L = self.lay[name]
-            nn.transpose_weights(self._w(name), L["cop"], L["cip"], self.WT[name], stream=self.stream)
+            nn.flip_weights(self._w(name), L["cop"], L["cip"], self.WF[name], stream=self.stream)
 
     def _w(self, name):
         L = self.lay[name]
@@ -235,7 +235,7 @@ class Network:
             mask = None
             if P["relu"]:
                 mask = self.yr[prev] if P["skip"] else self.y[prev]
-            nn.conv3d_bwd_data(self.dz[name], self.WT[name], self.batch, *self.ext_in[name], L["cip"],
+            nn.conv3d_bwd_data(self.dz[name], self.WF[name], self.batch, *self.ext_in[name], L["cip"],
                                L["s"], L["u"], add=self.gskip.get(prev), mask=mask,
                                da=self.gskip[P["skip"]] if P["skip"] else None, dzp=self.dz[prev],
                                stream=self.stream)
@@ -243,7 +243,7 @@ class Network:
     def step(self):
         self.t += 1
         nn.adam(self.P, self.M, self.V, self.G, self.t, self.lr, pb=self.Pb, stream=self.stream)
-        self._transpose()
+        self._flip()
 
     def train_step(self, xn, tn, with_loss=True):
         """One optimiser step on normalised inputs / targets; returns the

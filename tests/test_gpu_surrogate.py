@@ -75,6 +75,8 @@ CASES = [  # (ci, co, stride, up, n, d, h, w)
     (16, 16, 1, 1, 2, 5, 6, 7), (16, 32, 2, 1, 2, 7, 6, 5), (32, 64, 2, 1, 1, 6, 9, 4),
     (64, 64, 1, 1, 1, 4, 5, 6), (64, 32, 1, 2, 2, 3, 4, 5), (32, 16, 1, 2, 1, 5, 3, 4),
     (5, 16, 1, 1, 2, 6, 5, 7), (16, 5, 1, 1, 1, 5, 6, 4), (64, 16, 1, 1, 1, 9, 11, 13),
+    # several LDS halo tiles along every axis, with ragged ends
+    (32, 32, 1, 1, 2, 5, 19, 37), (16, 16, 1, 1, 1, 9, 17, 33),
 ]
 
 
@@ -125,8 +127,8 @@ def test_conv_data_gradient(case):
     dxa, _, _ = S.conv3d_backward(x, np.abs(wt), np.abs(dz), s, u)
     cip, cop = _pad(ci), _pad(co)
     W = _wdev(torch, wt, cop, cip)
-    WT = torch.empty((27, cip, cop), dtype=torch.bfloat16, device="cuda")
-    nn.transpose_weights(W, cop, cip, WT)
+    WT = torch.empty((cip, 27, cop), dtype=torch.bfloat16, device="cuda")
+    nn.flip_weights(W, cop, cip, WT)
     add = _bf(rng.standard_normal(dx.shape))
     mask = _bf(rng.standard_normal(dx.shape))
     _log(f"[gpu] conv data grad {case}")
