@@ -79,8 +79,8 @@ def lib():
         L.ora_grad_lap.argtypes = [C.c_int, dp, dp, dp]
         L.ora_chem_potential.restype = C.c_double
         L.ora_chem_potential.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
-        L.ora_viscous_force.argtypes = [C.c_int, dp, dp, C.c_double, dp, dp]
-        L.ora_collide_g.argtypes = [C.c_int, dp, dp, dp, C.c_double, C.c_double, dp]
+        L.ora_viscous_force.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, dp, dp]
+        L.ora_collide_g.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_double, dp]
         L.ora_phase_forcing.argtypes = [C.c_int, C.c_double, dp, C.c_double, dp]
         L.ora_collide_h.argtypes = [C.c_int, dp, C.c_double, dp, dp, C.c_double, C.c_double, dp]
         L.ora_collide_node.argtypes = [C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
@@ -113,8 +113,16 @@ def make_params(cfg: dict) -> Params:
     p.inlet_radius = float(cfg.get("inlet_radius", 0.0))
     p.inlet_u = float(cfg.get("inlet_u", 0.0))
     p.outlet_mode = _OUTLET[cfg.get("outlet_mode", "local")]
-    p.flags = 1 if cfg.get("clamp_phi", False) else 0
+    p.flags = (1 if cfg.get("clamp_phi", False) else 0) | (2 if _op(cfg) == "bgk" else 0)
     return p
+
+
+def _op(cfg):
+    """Collision operator of the hydrodynamic set: "wmrt" (default) or "bgk"."""
+    op = cfg.get("collision", "wmrt")
+    if op not in ("wmrt", "bgk"):
+        raise ValueError(f"collision must be 'wmrt' or 'bgk', not {op!r}")
+    return op
 
 
 def lattice(q: int):
@@ -249,21 +257,24 @@ def chem_potential(phi, lap, sigma, xi):
     return lib().ora_chem_potential(phi, lap, sigma, xi)
 
 
-def viscous_force(q, g, feq_, tau, gradrho):
+_OPS = {"wmrt": 0, "bgk": 1}
+
+
+def viscous_force(q, g, feq_, tau, gradrho, op="wmrt"):
     g, gp = _d(g)
     f, fp = _d(feq_)
     gr, grp = _d(np.asarray(gradrho, float).reshape(3))
     out = np.empty(3)
-    lib().ora_viscous_force(q, gp, fp, tau, grp, _d(out)[1])
+    lib().ora_viscous_force(q, _OPS[op], gp, fp, tau, grp, _d(out)[1])
     return out
 
 
-def collide_g(q, g, feq_, force, rho, tau):
+def collide_g(q, g, feq_, force, rho, tau, op="wmrt"):
     g, gp = _d(g)
     f, fp = _d(feq_)
     F, Fp = _d(np.asarray(force, float).reshape(3))
     out = np.empty(q)
-    lib().ora_collide_g(q, gp, fp, Fp, rho, tau, _d(out)[1])
+    lib().ora_collide_g(q, _OPS[op], gp, fp, Fp, rho, tau, _d(out)[1])
     return out
 
 

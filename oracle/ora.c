@@ -252,12 +252,16 @@ static void mrt_apply(const lattice_t* L, double s_nu, const double* x, double* 
 static double s_nu_of(double tau) { return 1.0 / (tau + 0.5); }
 
 /* Eq. viscous_force_wmrt: F_mu,i = -(nu/(cs^2 dt)) [sum_b e_bi e_bj (M^-1 S M (f - f^eq))_b] d_j rho,
- * with nu = tau cs^2 (Eq. kinematic_viscosity). */
-static void viscous_fn(const lattice_t* L, const double* g, const double* feq, double tau,
+ * with nu = tau cs^2 (Eq. kinematic_viscosity).
+ * op = ORA_OP_BGK: Eq. viscous_force_bgk, the same sum with (f - f^eq)/(tau + 1/2). */
+static void viscous_fn(const lattice_t* L, int op, const double* g, const double* feq, double tau,
                        const double* gradrho, double* fmu) {
   double x[QMAX], y[QMAX];
   for (int a = 0; a < L->q; ++a) x[a] = g[a] - feq[a];
-  mrt_apply(L, s_nu_of(tau), x, y);
+  if (op == ORA_OP_BGK)
+    for (int a = 0; a < L->q; ++a) y[a] = x[a] / (tau + 0.5);
+  else
+    mrt_apply(L, s_nu_of(tau), x, y);
   double nu = tau * CS2;
   for (int i = 0; i < 3; ++i) {
     double acc = 0.0;
@@ -270,13 +274,14 @@ static void viscous_fn(const lattice_t* L, const double* g, const double* feq, d
   }
 }
 
-void ora_viscous_force(int q, const double* g, const double* feq, double tau,
+void ora_viscous_force(int q, int op, const double* g, const double* feq, double tau,
                        const double* gradrho, double* fmu) {
-  viscous_fn(lattice_of(q), g, feq, tau, gradrho, fmu);
+  viscous_fn(lattice_of(q), op, g, feq, tau, gradrho, fmu);
 }
 
-/* Eqs. force_term, equilibrium_modified, mrt_collision, lbe_standard (collision part) */
-static void collide_g_fn(const lattice_t* L, const double* g, const double* feq, const double* F,
+/* Eqs. force_term, equilibrium_modified, mrt_collision, lbe_standard (collision part);
+ * op = ORA_OP_BGK: Eq. bgk_collision in place of Eq. mrt_collision. */
+static void collide_g_fn(const lattice_t* L, int op, const double* g, const double* feq, const double* F,
                          double rho, double tau, double* gplus) {
   double Fa[QMAX], y[QMAX] = {0}, om[QMAX];
   for (int a = 0; a < L->q; ++a) {
@@ -285,13 +290,16 @@ static void collide_g_fn(const lattice_t* L, const double* g, const double* feq,
     double fbar = feq[a] - 0.5 * Fa[a];
     y[a] = g[a] - fbar;
   }
-  mrt_apply(L, s_nu_of(tau), y, om);
+  if (op == ORA_OP_BGK)
+    for (int a = 0; a < L->q; ++a) om[a] = y[a] / (tau + 0.5);
+  else
+    mrt_apply(L, s_nu_of(tau), y, om);
   for (int a = 0; a < L->q; ++a) gplus[a] = g[a] - om[a] + Fa[a];
 }
 
-void ora_collide_g(int q, const double* g, const double* feq, const double* force, double rho,
+void ora_collide_g(int q, int op, const double* g, const double* feq, const double* force, double rho,
                    double tau, double* gplus) {
-  collide_g_fn(lattice_of(q), g, feq, force, rho, tau, gplus);
+  collide_g_fn(lattice_of(q), op, g, feq, force, rho, tau, gplus);
 }
 
 /* Eq. forcing_term.  reading: the unit normal is regularised as
@@ -352,11 +360,14 @@ static void body_force_fn(const ora_params* P, double rho, double* Fb) {
  *    re-evaluated from it (Alg. 1, second procedure).
  * reading: the printed algorithms evaluate the viscous force twice, once with
  * the stored velocity (macroscopic update) and once with the updated one
- * (collision); both are kept. */
+ * (collision); both are kept.
+ * flags bit 1 selects the BGK operator and its viscous force for the
+ * hydrodynamic set (the phase-field set is single-relaxation either way). */
 void ora_collide_node(const ora_params* P, const double* h, const double* g,
                       const double* u_prev, const double* phin,
                       double* hplus, double* gplus, double* u_new) {
   const lattice_t* L = lattice_of(P->q);
+  const int op = (P->flags & 2) ? ORA_OP_BGK : ORA_OP_WMRT;
   const double phi = phin[0];
   const double phi_c = (P->flags & 1) ? clamp01(phi) : phi;
   const double rho = P->rho_l + phi_c * (P->rho_h - P->rho_l); /* phi_L = 0 */
@@ -377,7 +388,7 @@ void ora_collide_node(const ora_params* P, const double* h, const double* g,
   /* macroscopic update: viscous force from the stored velocity */
   double feq_old[QMAX], fmu[3], F[3];
   feq_fn(L, pstar, u_prev, feq_old);
-  viscous_fn(L, g, feq_old, tau, gradrho, fmu);
+  viscous_fn(L, op, g, feq_old, tau, gradrho, fmu);
   for (int d = 0; d < 3; ++d) {
     double Fp = -pstar * CS2 * gradrho[d]; /* Eq. pressure_force */
     F[d] = Fs[d] + Fb[d] + Fp + fmu[d];    /* Eq. total_force */
@@ -393,12 +404,12 @@ void ora_collide_node(const ora_params* P, const double* h, const double* g,
   /* hydrodynamic collision */
   double feq_new[QMAX], fmu2[3], F2[3];
   feq_fn(L, pstar, u_new, feq_new);
-  viscous_fn(L, g, feq_new, tau, gradrho, fmu2);
+  viscous_fn(L, op, g, feq_new, tau, gradrho, fmu2);
   for (int d = 0; d < 3; ++d) {
     double Fp = -pstar * CS2 * gradrho[d];
     F2[d] = Fs[d] + Fb[d] + Fp + fmu2[d];
   }
-  collide_g_fn(L, g, feq_new, F2, rho, tau, gplus);
+  collide_g_fn(L, op, g, feq_new, F2, rho, tau, gplus);
 }
 
 /* ------------------------------------------------------------------------ */

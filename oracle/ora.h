@@ -36,7 +36,8 @@ typedef struct {
   double inlet_radius;
   double inlet_u;        /* plug speed along the inward normal */
   int outlet_mode;       /* 0 local, 1 plane maximum, 2 plane average */
-  int flags;             /* bit 0: clamp phi to [0,1] inside rho(phi), tau(phi) */
+  int flags;             /* bit 0: clamp phi to [0,1] inside rho(phi), tau(phi);
+                            bit 1: BGK collision and viscous force for g (else WMRT) */
 } ora_params;
 
 typedef struct ora_sim ora_sim;
@@ -69,9 +70,12 @@ void ora_feq(int q, double pstar, const double* u, double* feq);
 void ora_heq(int q, double phi, const double* u, double* heq);
 void ora_grad_lap(int q, const double* phin, double* grad, double* lap);
 double ora_chem_potential(double phi, double lap, double sigma, double xi);
-void ora_viscous_force(int q, const double* g, const double* feq, double tau,
+/* op: collision operator of the hydrodynamic set */
+#define ORA_OP_WMRT 0
+#define ORA_OP_BGK 1
+void ora_viscous_force(int q, int op, const double* g, const double* feq, double tau,
                        const double* gradrho, double* fmu);
-void ora_collide_g(int q, const double* g, const double* feq, const double* force,
+void ora_collide_g(int q, int op, const double* g, const double* feq, const double* force,
                    double rho, double tau, double* gplus);
 void ora_phase_forcing(int q, double phi, const double* gradphi, double xi, double* fphi);
 void ora_collide_h(int q, const double* h, double phi, const double* u, const double* gradphi,

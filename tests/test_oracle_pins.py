@@ -238,6 +238,30 @@ def test_wmrt_is_bgk_at_tau_half(q):
 
 
 @pytest.mark.parametrize("q", LATTICES)
+def test_bgk_operator_reduces_to_wmrt_at_tau_half(q):
+    """The selectable BGK operator (Eqs. bgk_collision, viscous_force_bgk)
+    and WMRT coincide when s_nu = 1, and differ otherwise; with f^eq built
+    from p* = sum g, BGK keeps sum g (sum F_a = 0)."""
+    rng = np.random.default_rng(8)
+    e, w, *_ = oracle.lattice(q)
+    u = _rand_u(rng, q)
+    g = oracle.feq(q, 0.01, u) + 1e-3 * rng.standard_normal(q)
+    feq = oracle.feq(q, g.sum(), u)
+    F = _rand_u(rng, q, 1e-4)
+    gr = _rand_u(rng, q, 0.3)
+    for tau, same in ((0.5, True), (0.05, False), (1.3, False)):
+        a = oracle.collide_g(q, g, feq, F, 0.7, tau, op="bgk")
+        b = oracle.collide_g(q, g, feq, F, 0.7, tau, op="wmrt")
+        fa = oracle.viscous_force(q, g, feq, tau, gr, op="bgk")
+        fb = oracle.viscous_force(q, g, feq, tau, gr, op="wmrt")
+        if same:
+            assert np.abs(a - b).max() < 1e-16 and np.abs(fa - fb).max() < 1e-17
+        else:
+            assert np.abs(a - b).max() > 1e-6 and np.abs(fa - fb).max() > 1e-6 * np.abs(fb).max()
+        assert abs(a.sum() - g.sum()) < 1e-15
+
+
+@pytest.mark.parametrize("q", LATTICES)
 def test_viscous_force_closed_form(q):
     """F_mu = -tau [s dev(Pi) + tr(Pi)/d I] grad rho, Pi = sum e e (g - feq)."""
     rng = np.random.default_rng(6)
