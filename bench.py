@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--tile", default="", help="bx,by launch shape of the fused kernel")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Weber sweep")
+    ap.add_argument("--no-bgk", action="store_true", help="skip the FP32 run with the BGK operator")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training step")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
@@ -248,6 +249,17 @@ def main():
                      "step_kernel_ms": round(kt2[1], 4),
                      "step_kernel_GBs": round(bk2 * N / (kt2[1] * 1e-3) / 1e9, 1)}
         print(f"[bench] {st} {forms[st]}", file=sys.stderr, flush=True)
+        del s2
+        torch.cuda.empty_cache()
+
+    if not args.no_bgk:  # the selectable single-relaxation operator on the same workload
+        n2 = max(20, args.steps // 2)
+        s2, dt2, kt2, _, _ = run_gpu(dict(cfg, collision="bgk"), phi0, u0, "fp32", n2, 5, tile,
+                                     not args.no_autotune)
+        forms["bgk_fp32"] = {"MLUPS": round(N * n2 / dt2 / 1e6, 1),
+                             "step_kernel_ms": round(kt2[1], 4),
+                             "step_kernel_GBs": round(b_k * N / (kt2[1] * 1e-3) / 1e9, 1)}
+        print(f"[bench] bgk_fp32 {forms['bgk_fp32']}", file=sys.stderr, flush=True)
         del s2
         torch.cuda.empty_cache()
 

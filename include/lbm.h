@@ -74,6 +74,12 @@ typedef enum { LBM_OUTLET_LOCAL = 0, LBM_OUTLET_MAX = 1, LBM_OUTLET_AVERAGE = 2 
 
 /* variant_flags: clamp phi to [0,1] inside rho(phi) and tau(phi) only */
 #define LBM_VF_CLAMP_PHI 1u
+/* variant_flags: the hydrodynamic set relaxes with the single-relaxation BGK
+ * operator (Eq. bgk_collision, rate 1/(tau + 1/2)) and the viscous force
+ * takes its BGK form (Eq. viscous_force_bgk), in place of the WMRT operator
+ * and Eq. viscous_force_wmrt.  The phase-field set is unchanged.  All domains
+ * of a batch must agree (LBM_EINVAL otherwise). */
+#define LBM_VF_BGK 2u
 
 /* Problem statement in lattice units (dx = dt = 1, cs^2 = 1/3). */
 typedef struct {

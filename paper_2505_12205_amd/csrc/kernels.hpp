@@ -3,7 +3,8 @@
 // One step at parity P (P = steps % 2) is, over a table of domains,
 //   kb_interior<P, PHI>, kb_faces<P, PHI>: phi(x) = sum_a h_a(x) (Eq. phase_field_variable)
 //   kb_interior<P, STEP>, kb_faces<P, STEP>: stencil of phi, macroscopic update,
-//       both collisions and the in-place AA streaming of both population sets
+//       both collisions and the in-place AA streaming of both population sets;
+//       the hydrodynamic set relaxes with WMRT, or with BGK (template flag)
 //   kb_outlet<P>: convective outflow plane (only with an outlet face)
 // Nodes off the y and z faces of non-periodic axes take the tiled fast path
 // with precomputed neighbour offsets (x walls included, with a per-lane slot
@@ -489,8 +490,9 @@ struct Stress {  // second moments sum g e e
 // Viscous force of the WMRT operator (Eq. viscous_force_wmrt) in the closed
 // form -tau [s dev(Pi) + tr(Pi)/d I] grad rho, Pi = sum e e (g - f^eq(p*, u)):
 // the weighted moment basis makes M^-1 S M act as s on the deviatoric
-// second moments and as 1 on their trace.
-template <int D>
+// second moments and as 1 on their trace.  BGK (Eq. viscous_force_bgk):
+// -tau s Pi grad rho, the trace relaxed at s as well.
+template <int D, bool BGK>
 __device__ __forceinline__ void viscous_force(const Stress& S, float p, const float u[3], float tau,
                                               float s, const float gr[3], float F[3]) {
   const float p3 = p * (1.0f / 3.0f);
@@ -500,7 +502,7 @@ __device__ __forceinline__ void viscous_force(const Stress& S, float p, const fl
   const float xy = S.xy - u[0] * u[1];
   const float yz = (D == 3) ? S.yz - u[1] * u[2] : 0.0f;
   const float xz = (D == 3) ? S.xz - u[0] * u[2] : 0.0f;
-  const float tr = (xx + yy + zz) * (1.0f / D);
+  const float tr = BGK ? 0.0f : (xx + yy + zz) * (1.0f / D);
   const float Txx = s * (xx - tr) + tr, Tyy = s * (yy - tr) + tr, Tzz = s * (zz - tr) + tr;
   const float Txy = s * xy, Tyz = s * yz, Txz = s * xz;
   F[0] = -tau * (Txx * gr[0] + Txy * gr[1] + Txz * gr[2]);
@@ -524,14 +526,15 @@ __device__ __forceinline__ void add_moments(int a, float v, float& p, float j[3]
 // everything both collisions need, from the stencil and the moments of g
 struct NodeCtx {
   float phi, u[3], uu, om, tn[3];  // phase-field collision
-  float p, f3r, F[3];              // hydrodynamic equilibrium and forcing
+  float p, f3r, F[3], s;           // hydrodynamic equilibrium, forcing, relaxation rate
   float cxx, cyy, czz, cxy, cyz, cxz;  // (1 - s) times the stress-projection coefficients
 };
 
 // Macroscopic update (Eqs. density_interpolation, chemical_potential,
 // surface_tension_force, density_gradient_phase_field, relaxation_time,
-// pressure_force, total_force, velocity_update) and the collision constants.
-template <int Q>
+// pressure_force, total_force, velocity_update) and the collision constants
+// of the WMRT operator, or of the BGK operator (BGK).
+template <int Q, bool BGK>
 __device__ __forceinline__ void macro(const KParams& P, float phi, const float gr[3], float lap, float p,
                                       const float j[3], const Stress& S, const float up[3], NodeCtx& X) {
   constexpr int D = Lat<Q>::D;
@@ -552,14 +555,14 @@ __device__ __forceinline__ void macro(const KParams& P, float phi, const float g
   const float p3 = p * (1.0f / 3.0f);
   // velocity with the viscous force evaluated at the stored velocity
   float Fm[3];
-  viscous_force<D>(S, p, up, tau, s, grho, Fm);
+  viscous_force<D, BGK>(S, p, up, tau, s, grho, Fm);
   float u[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) u[d] = j[d] + 0.5f * (Fsb[d] - p3 * grho[d] + Fm[d]) * inv_rho;
   if (D == 2) u[2] = 0.0f;
   // collision force with the viscous force re-evaluated at u^n
   float Fc[3];
-  viscous_force<D>(S, p, u, tau, s, grho, Fc);
+  viscous_force<D, BGK>(S, p, u, tau, s, grho, Fc);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     X.u[d] = u[d];
@@ -568,6 +571,7 @@ __device__ __forceinline__ void macro(const KParams& P, float phi, const float g
   X.uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   X.phi = phi;
   X.p = p;
+  X.s = s;
   X.f3r = 3.0f * inv_rho;
   // phase-field forcing direction (Eq. forcing_term)
   const float theta = (1.0f - 4.0f * (phi - 0.5f) * (phi - 0.5f)) * P.inv_xi;
@@ -576,6 +580,7 @@ __device__ __forceinline__ void macro(const KParams& P, float phi, const float g
   X.tn[1] = theta * gr[1] * nrm;
   X.tn[2] = theta * gr[2] * nrm;
   X.om = P.omega_h;
+  if (BGK) return;  // BGK relaxes every population at s: no projection
   // WMRT: only the deviatoric second moments of g - fbar, dev(Pi - u u), keep
   // a (1 - s) share; the projection coefficients follow
   const float dxx = S.xx - u[0] * u[0], dyy = S.yy - u[1] * u[1];
@@ -614,15 +619,17 @@ __device__ __forceinline__ float h_post(const NodeCtx& X, int a, float ha) {
 }
 
 // post-collision g_a: f^eq + F_a/2 + (1 - s) P(g - fbar)_a, the closed form of
-// Eqs. lbe_standard, mrt_collision, equilibrium_modified, force_term
-template <int Q>
-__device__ __forceinline__ float g_post(const NodeCtx& X, int a) {
+// Eqs. lbe_standard, mrt_collision, equilibrium_modified, force_term; BGK
+// (Eq. bgk_collision): g_a - s (g_a - fbar_a) + F_a = (1 - s) g_a + s f^eq_a + (1 - s/2) F_a
+template <int Q, bool BGK>
+__device__ __forceinline__ float g_post(const NodeCtx& X, int a, float ga) {
   using L = Lat<Q>;
   const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
   const float w = L::w[a];
   const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
   const float feq = w * (X.p + 3.0f * eu + 4.5f * eu * eu - 1.5f * X.uu);
   const float Fa = w * X.f3r * (ex * X.F[0] + ey * X.F[1] + ez * X.F[2]);
+  if (BGK) return (1.0f - X.s) * ga + X.s * feq + (1.0f - 0.5f * X.s) * Fa;
   float proj = 0.0f;
   if (ex) proj += X.cxx;
   if (ey) proj += X.cyy;
@@ -741,7 +748,7 @@ __device__ __forceinline__ bool on_special_face(const KParams& P, const int c[3]
 // sum to 1 + O(1e-8)) would leave a small systematic mass drift per step, so
 // the node's mass is restored on the rest population with compensated sums
 // (a zero correction in exact arithmetic).
-template <int Q, int ST, int ODD, bool NT, bool WALL>
+template <int Q, int ST, int ODD, bool NT, bool WALL, bool BGK>
 __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, const int c[3]) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -780,8 +787,10 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     return (size_t)pop0 * NN;
   };
 
-  // hydrodynamic moments, opposite pairs summed and differenced
+  // hydrodynamic moments, opposite pairs summed and differenced (BGK keeps
+  // the populations for the collision)
   float g0 = C::ld_g(Gp, (unsigned)node, L::w[0]);
+  float gv[Q];
   float p = g0, j[3] = {0.f, 0.f, 0.f};
   Stress S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -794,6 +803,10 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const Ty* Gb = Gp + sbase(a, ib, rb);
     const float ga = C::ld_g(Ga, ia, L::w[a]);
     const float gb = C::ld_g(Gb, ib, L::w[b]);
+    if (BGK) {
+      gv[a] = ga;
+      gv[b] = gb;
+    }
     const float s = ga + gb, d = ga - gb;
     p += s;
     if (L::ex[a]) { j[0] += L::ex[a] * d; S.xx += s; }
@@ -808,7 +821,7 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   up[1] = B.u[N + node];
   up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
   NodeCtx X;
-  macro<Q>(P, phi, gr, lap, p, j, S, up, X);
+  macro<Q, BGK>(P, phi, gr, lap, p, j, S, up, X);
   B.u[node] = X.u[0];
   B.u[N + node] = X.u[1];
   if (D == 3) B.u[2 * N + node] = X.u[2];
@@ -824,7 +837,8 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   const float h0 = C::ld_h(Hp, (unsigned)node, L::w[0], ref);
   {
     const float w = L::w[0];
-    const float g0p = w * gA;  // e_0 = 0: no forcing, no stress projection
+    // e_0 = 0: no forcing, no stress projection
+    const float g0p = BGK ? (1.0f - X.s) * g0 + X.s * (w * gA) : w * gA;
     C::template st_g<NT>(Gp, (unsigned)node, g0p, 1.0f / w);
   }
   const float d0 = om * (X.phi * L::w[0] * hB - h0);
@@ -851,19 +865,27 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
     const float eu2 = eu * eu;
     // hydrodynamic set
-    float proj = 0.0f;
-    if (ex) proj += X.cxx;
-    if (ey) proj += X.cyy;
-    if (ez) proj += X.czz;
-    if (ex && ey) proj += (ex * ey) * X.cxy;
-    if (ey && ez) proj += (ey * ez) * X.cyz;
-    if (ex && ez) proj += (ex * ez) * X.cxz;
-    if (D == 2) proj *= (1.0f / w);  // the D2Q9 projection is not weighted
     const float eF = ex * X.F[0] + ey * X.F[1] + ez * X.F[2];
-    const float gsym = w * (gA + 4.5f * eu2 + proj);
-    const float ganti = w * (3.0f * eu + hf * eF);
-    C::template st_g<NT>(Gb, ib, gsym + ganti, 1.0f / w);  // a goes where b was read
-    C::template st_g<NT>(Ga, ia, gsym - ganti, 1.0f / w);
+    if (BGK) {  // (1 - s) g + s f^eq + (1 - s/2) F_a, even and odd parts
+      const float sr = X.s;
+      const float gsym = sr * w * (gA + 4.5f * eu2);
+      const float ganti = w * (sr * 3.0f * eu + (2.0f - sr) * hf * eF);
+      C::template st_g<NT>(Gb, ib, (1.0f - sr) * gv[a] + gsym + ganti, 1.0f / w);  // a goes where b was read
+      C::template st_g<NT>(Ga, ia, (1.0f - sr) * gv[b] + gsym - ganti, 1.0f / w);
+    } else {
+      float proj = 0.0f;
+      if (ex) proj += X.cxx;
+      if (ey) proj += X.cyy;
+      if (ez) proj += X.czz;
+      if (ex && ey) proj += (ex * ey) * X.cxy;
+      if (ey && ez) proj += (ey * ez) * X.cyz;
+      if (ex && ez) proj += (ex * ez) * X.cxz;
+      if (D == 2) proj *= (1.0f / w);  // the D2Q9 projection is not weighted
+      const float gsym = w * (gA + 4.5f * eu2 + proj);
+      const float ganti = w * (3.0f * eu + hf * eF);
+      C::template st_g<NT>(Gb, ib, gsym + ganti, 1.0f / w);  // a goes where b was read
+      C::template st_g<NT>(Ga, ia, gsym - ganti, 1.0f / w);
+    }
     // phase-field set
     const float pw = X.phi * w;
     const float hsym = pw * (hB + 4.5f * eu2);
@@ -885,7 +907,7 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
 }
 
 // Nodes on wall, inlet or outlet faces: general slot resolution with arrays.
-template <int Q, int ST, int ODD, bool NT>
+template <int Q, int ST, int ODD, bool NT, bool BGK>
 __device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, const int c[3]) {
   using L = Lat<Q>;
   constexpr int D = L::D;
@@ -914,7 +936,7 @@ __device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, c
   up[1] = B.u[N + node];
   up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
   NodeCtx X;
-  macro<Q>(P, phi, gr, lap, p, j, S, up, X);
+  macro<Q, BGK>(P, phi, gr, lap, p, j, S, up, X);
   B.u[node] = X.u[0];
   B.u[N + node] = X.u[1];
   if (D == 3) B.u[2 * N + node] = X.u[2];
@@ -924,7 +946,7 @@ __device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, c
   for (int a = 0; a < Q; ++a) {
     int sp, sn;
     if (resolve_dst<Q, ODD>(P, c, a, sp, sn))
-      C::template st_g<NT>(Gw, (size_t)sp * N + sn, g_post<Q>(X, a), 1.0f / L::w[a]);
+      C::template st_g<NT>(Gw, (size_t)sp * N + sn, g_post<Q, BGK>(X, a, g[a]), 1.0f / L::w[a]);
   }
   float pre_s = 0.f, pre_c = 0.f, post_s = 0.f, post_c = 0.f;
 #pragma unroll
@@ -1100,7 +1122,7 @@ struct DomDev {
 // Persistent, chunked launch over the tile list of all domains: each block
 // walks a contiguous chunk of tiles (contiguous per XCD after the remap), so
 // neighbouring tiles of one domain share an L2.
-template <int Q, int ST, int ODD, bool NT, bool PHI, bool WALL>
+template <int Q, int ST, int ODD, bool NT, bool PHI, bool WALL, bool BGK>
 __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D, const int* __restrict__ tile_dom,
                                                    int ntiles, int chunk, int bx, int by) {
   const int L = xcd_remap(blockIdx.x, gridDim.x);
@@ -1120,7 +1142,7 @@ __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D,
     if (PHI)
       phi_fast<Q, ST, ODD, WALL>(dm.K, dm.B[ODD], c);
     else
-      step_fast<Q, ST, ODD, NT, WALL>(dm.K, dm.B[ODD], c);
+      step_fast<Q, ST, ODD, NT, WALL, BGK>(dm.K, dm.B[ODD], c);
   }
 }
 
@@ -1137,7 +1159,7 @@ __device__ __forceinline__ int find_dom(const DomDev* __restrict__ D, int ndom, 
   return lo;
 }
 
-template <int Q, int ST, int ODD, bool NT, bool PHI>
+template <int Q, int ST, int ODD, bool NT, bool PHI, bool BGK>
 __global__ __launch_bounds__(256) void kb_faces(const DomDev* __restrict__ D, int ndom, int nface) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nface) return;
@@ -1148,7 +1170,7 @@ __global__ __launch_bounds__(256) void kb_faces(const DomDev* __restrict__ D, in
   if (PHI)
     phi_general<Q, ST, ODD>(dm.K, dm.B[ODD], c);
   else
-    step_general<Q, ST, ODD, NT>(dm.K, dm.B[ODD], c);
+    step_general<Q, ST, ODD, NT, BGK>(dm.K, dm.B[ODD], c);
 }
 
 template <int Q, int ST, int ODD>

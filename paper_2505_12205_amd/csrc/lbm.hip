@@ -67,6 +67,7 @@ int validate(const lbm_params* p) {
   if (p->storage < LBM_FP32 || p->storage > LBM_BF16_DEV) return fail(LBM_EINVAL, "unknown storage");
   if (p->body_force != LBM_FB_RHO_G && p->body_force != LBM_FB_RHO_MINUS_RHOL_G)
     return fail(LBM_EINVAL, "unknown body force");
+  if (p->variant_flags & ~(LBM_VF_CLAMP_PHI | LBM_VF_BGK)) return fail(LBM_EINVAL, "unknown variant flag");
   const int ndim = p->lattice == LBM_D2Q9 ? 2 : 3;
   const int ax = axis_of(p->lattice);
   for (int d = 0; d < 3; ++d) {
@@ -213,6 +214,7 @@ struct LaunchSet {
   int ndom = 0, ntiles = 0, nface = 0, nplane = 0;
   int bx = 64, by = 4, bpc = 4, nt = 0;
   bool wall = false;  // some domain has lateral wall faces (wall lanes in the tiles)
+  bool bgk = false;   // BGK operator for the hydrodynamic set (the same for every domain)
   int grid = 1, chunk = 1;
 };
 
@@ -277,7 +279,10 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   std::vector<int> tile_dom;
   int tb = 0, fb = 0, pb = 0;
   bool wall = false;
+  const bool bgk = (v[0]->P.variant_flags & LBM_VF_BGK) != 0;
   for (int d = 0; d < n; ++d) {
+    if (((v[d]->P.variant_flags & LBM_VF_BGK) != 0) != bgk)
+      return fail(LBM_EINVAL, "all domains of a batch must use the same collision operator");
     lbm_sim* s = v[d];
     DomDev& m = dom[d];
     memset(&m, 0, sizeof m);
@@ -304,6 +309,7 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   }
   free_launch(ls);
   ls.wall = wall;
+  ls.bgk = bgk;
   ls.ndom = n;
   ls.ntiles = tb;
   ls.nface = fb;
@@ -333,28 +339,36 @@ template <int Q, int ST, int PAR>
 void launch_phi_set(const LaunchSet& ls, hipStream_t st) {
   const dim3 gi(ls.grid), bi(ls.bx * ls.by);
   if (ls.ntiles && ls.wall)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, true, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
                        ls.ntiles, ls.chunk, ls.bx, ls.by);
   else if (ls.ntiles)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, false, true, false, false>), gi, bi, 0, st, ls.d_dom,
+                       ls.d_tile, ls.ntiles, ls.chunk, ls.bx, ls.by);
+  if (ls.nface)
+    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, false, true, false>), dim3((ls.nface + 255) / 256), dim3(256), 0,
+                       st, ls.d_dom, ls.ndom, ls.nface);
+}
+
+template <int Q, int ST, int PAR, bool NT, bool BGK>
+void launch_collide_op(const LaunchSet& ls, hipStream_t st) {
+  const dim3 gi(ls.grid), bi(ls.bx * ls.by);
+  if (ls.ntiles && ls.wall)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, true, BGK>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
+                       ls.ntiles, ls.chunk, ls.bx, ls.by);
+  else if (ls.ntiles)
+    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, false, BGK>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
                        ls.ntiles, ls.chunk, ls.bx, ls.by);
   if (ls.nface)
-    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, false, true>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NT, false, BGK>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
                        ls.d_dom, ls.ndom, ls.nface);
 }
 
 template <int Q, int ST, int PAR, bool NT>
 void launch_collide_set(const LaunchSet& ls, hipStream_t st) {
-  const dim3 gi(ls.grid), bi(ls.bx * ls.by);
-  if (ls.ntiles && ls.wall)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, true>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
-                       ls.ntiles, ls.chunk, ls.bx, ls.by);
-  else if (ls.ntiles)
-    hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, false>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
-                       ls.ntiles, ls.chunk, ls.bx, ls.by);
-  if (ls.nface)
-    hipLaunchKernelGGL((kb_faces<Q, ST, PAR, NT, false>), dim3((ls.nface + 255) / 256), dim3(256), 0, st,
-                       ls.d_dom, ls.ndom, ls.nface);
+  if (ls.bgk)
+    launch_collide_op<Q, ST, PAR, NT, true>(ls, st);
+  else
+    launch_collide_op<Q, ST, PAR, NT, false>(ls, st);
 }
 
 // one step of parity `par`: phase-field pass, fused step, outlet planes;
@@ -897,6 +911,8 @@ int batch_validate(int ndom, const lbm_params* p) {
     if (rc) return fail(rc, "domain " + std::to_string(d) + ": " + g_err);
     if (p[d].lattice != p[0].lattice || p[d].storage != p[0].storage)
       return fail(LBM_EINVAL, "all domains of a batch share lattice and storage");
+    if ((p[d].variant_flags ^ p[0].variant_flags) & LBM_VF_BGK)
+      return fail(LBM_EINVAL, "all domains of a batch must use the same collision operator");
   }
   return LBM_OK;
 }

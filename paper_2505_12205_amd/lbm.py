@@ -21,6 +21,8 @@ _BODY = {"rho": 0, "rho_minus_rhol": 1}
 _OUTLET = {"local": 0, "max": 1, "average": 2}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 VF_CLAMP_PHI = 1
+VF_BGK = 2
+COLLISION = ("wmrt", "bgk")  # operator of the hydrodynamic set (cfg["collision"])
 
 
 class LbmError(RuntimeError):
@@ -124,7 +126,10 @@ def make_params(cfg: dict, storage: str = "fp32") -> Params:
     p.inlet_u = float(cfg.get("inlet_u", 0.0))
     p.outlet_mode = _OUTLET[cfg.get("outlet_mode", "local")]
     p.storage = STORAGE[storage]
-    p.variant_flags = VF_CLAMP_PHI if cfg.get("clamp_phi", False) else 0
+    op = cfg.get("collision", "wmrt")
+    if op not in COLLISION:
+        raise ValueError(f"collision must be one of {COLLISION}, not {op!r}")
+    p.variant_flags = (VF_CLAMP_PHI if cfg.get("clamp_phi", False) else 0) | (VF_BGK if op == "bgk" else 0)
     return p
 
 

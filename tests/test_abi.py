@@ -106,6 +106,30 @@ def test_batch_layout_and_validation_on_host():
     mixed = (lbm.Params * 2)(lbm.make_params(doms[0][0], "fp32"), lbm.make_params(d2, "fp32"))
     assert lbm.lib.lbm_batch_state_bytes(2, mixed, C.byref(n)) == -1
     assert lbm.lib.lbm_batch_state_bytes(0, arr, C.byref(n)) == -1
+    # one collision operator per batch
+    mixed = (lbm.Params * 2)(lbm.make_params(doms[0][0], "fp16"),
+                             lbm.make_params(dict(doms[1][0], collision="bgk"), "fp16"))
+    assert lbm.lib.lbm_batch_state_bytes(2, mixed, C.byref(n)) == -1
+    assert b"collision operator" in lbm.lib.lbm_last_error()
+    both = (lbm.Params * 2)(*[lbm.make_params(dict(d[0], collision="bgk"), "fp16") for d in doms])
+    assert lbm.lib.lbm_batch_state_bytes(2, both, C.byref(n)) == 0
+
+
+def test_collision_operator_selection_on_host():
+    """cfg["collision"] sets the BGK variant flag; unknown names and unknown
+    flag bits are rejected."""
+    from paper_2505_12205_amd import lbm
+    from paper_2505_12205_amd import workloads as W
+    cfg, _, _ = W.drop2d(n=16)
+    assert lbm.make_params(cfg).variant_flags == 0
+    assert lbm.make_params(dict(cfg, collision="bgk")).variant_flags == lbm.VF_BGK
+    assert lbm.make_params(dict(cfg, collision="bgk", clamp_phi=True)).variant_flags == lbm.VF_BGK | lbm.VF_CLAMP_PHI
+    with pytest.raises(ValueError):
+        lbm.make_params(dict(cfg, collision="mrt"))
+    p = lbm.make_params(cfg)
+    p.variant_flags = 4
+    n = C.c_size_t()
+    assert lbm.lib.lbm_state_bytes(C.byref(p), C.byref(n)) == -1
 
 
 def test_regime_helpers():
