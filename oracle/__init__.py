@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ora.c")
+_SRC_DROPS = os.path.join(_HERE, "drops.c")
 _LIB = os.path.join(_HERE, "libora.so")
 
 PERIODIC, NOSLIP, FREESLIP, INLET, OUTLET = 0, 1, 2, 3, 4
@@ -28,10 +29,10 @@ _OUTLET = {"local": 0, "max": 1, "average": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile ora.c into libora.so with gcc (IEEE double, no fast-math)."""
+    """Compile ora.c and drops.c into libora.so with gcc (IEEE double, no fast-math)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-Wno-unused-function", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        cmd = ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-function", _SRC, _SRC_DROPS, "-o", _LIB + ".tmp", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -84,6 +85,8 @@ def lib():
         L.ora_phase_forcing.argtypes = [C.c_int, C.c_double, dp, C.c_double, dp]
         L.ora_collide_h.argtypes = [C.c_int, dp, C.c_double, dp, dp, C.c_double, C.c_double, dp]
         L.ora_collide_node.argtypes = [C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
+        L.ora_label.argtypes = [fp, C.c_int, C.c_int, C.c_int, C.c_uint, C.c_float, ip]
+        L.ora_components.argtypes = [ip, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, ip, ip, dp]
         _lib = L
     return _lib
 
@@ -306,3 +309,44 @@ def collide_node(cfg, h, g, u_prev, phin):
     uo = np.empty(3)
     lib().ora_collide_node(C.byref(p), hp, gp, up, pnp, _d(ho)[1], _d(go)[1], _d(uo)[1])
     return ho, go, uo
+
+
+# ---------------------------------------------------------------------------
+# drop-size diagnostic (drops.c)
+# ---------------------------------------------------------------------------
+
+def label(phi, periodic=(False, False, False), thr=0.5):
+    """Connected components of {phi > thr} of a [nz, ny, nx] field (face
+    connectivity, axes x, y, z wrapping where periodic): int32 labels, each
+    the smallest node index of its component, -1 outside the liquid."""
+    phi = np.ascontiguousarray(np.asarray(phi, dtype=np.float32))
+    if phi.ndim == 2:
+        phi = phi[None]
+    nz, ny, nx = phi.shape
+    out = np.empty(phi.shape, np.int32)
+    mask = sum(1 << d for d in range(3) if periodic[d])
+    rc = lib().ora_label(phi.ctypes.data_as(C.POINTER(C.c_float)), nx, ny, nz, mask, float(thr),
+                         out.ctypes.data_as(C.POINTER(C.c_int)))
+    if rc != 0:
+        raise RuntimeError(f"ora_label failed ({rc})")
+    return out
+
+
+def components(lab, axis=2):
+    """Per component, in ascending order of label: dict of root, size (node
+    count), lo / hi (extent along axis: 0 = x, 1 = y, 2 = z) and deq (the
+    equivalent sphere diameter in 3D, disc diameter when nz = 1)."""
+    lab = np.ascontiguousarray(np.asarray(lab, dtype=np.int32))
+    nz, ny, nx = lab.shape
+    cap = int((lab.reshape(-1) == np.arange(lab.size)).sum())
+    ip = C.POINTER(C.c_int)
+    arrs = {k: np.zeros(max(cap, 1), np.int32) for k in ("root", "size", "lo", "hi")}
+    deq = np.zeros(max(cap, 1))
+    nc = lib().ora_components(lab.ctypes.data_as(ip), nx, ny, nz, axis, cap,
+                              *[arrs[k].ctypes.data_as(ip) for k in ("root", "size", "lo", "hi")],
+                              deq.ctypes.data_as(C.POINTER(C.c_double)))
+    if nc != cap:
+        raise RuntimeError(f"ora_components: {nc} components, expected {cap}")
+    out = {k: v[:nc] for k, v in arrs.items()}
+    out["deq"] = deq[:nc]
+    return out
