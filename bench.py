@@ -117,6 +117,36 @@ def run_surrogate(steps=10, batch=32):
             "batch": batch, "window": [5, 192, 48, 48]}
 
 
+def run_drops(reps=20):
+    """Drop-size diagnostic on the breaking-jet field of the jet workload's
+    size (192 x 192 x 768): labelling of {phi > 1/2} and the component
+    statistics, wall time per call (each call synchronises)."""
+    import torch
+    from paper_2505_12205_amd import drops as D
+    from paper_2505_12205_amd import workloads as W
+    phi_h, placed = W.breakup_field()
+    phi = torch.from_numpy(phi_h).cuda()
+    ws = D.workspace(phi_h.shape)
+    lab = torch.empty(phi_h.shape, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        D.label(phi, ws=ws, out=lab)
+        c = D.components(lab, axis=2, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        D.label(phi, ws=ws, out=lab)
+    t_label = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c = D.components(lab, axis=2, ws=ws)
+    t_comp = (time.perf_counter() - t0) / reps
+    n = phi.numel()
+    return {"nodes": n, "components": int(len(c["root"])), "drops_placed": len(placed),
+            "label_ms": round(t_label * 1e3, 3), "components_ms": round(t_comp * 1e3, 3),
+            "label_GBs_algorithmic": round(8.0 * n / t_label / 1e9, 1),
+            "label_Gnodes_per_s": round(n / t_label / 1e9, 2)}
+
+
 def counted_traffic():
     """HBM bytes per launch of the fused FP32 step from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
@@ -195,6 +225,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=8, help="batched launch with --tile")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only time the surrogate's training step (for profiling it alone)")
+    ap.add_argument("--drops-only", action="store_true",
+                    help="only run the drop-size diagnostic (for profiling it alone)")
+    ap.add_argument("--no-drops", action="store_true", help="skip the drop-size diagnostic")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
@@ -215,6 +248,9 @@ def main():
         return
     if args.surrogate_only:
         print(json.dumps({"surrogate_bf16_mfma": run_surrogate(steps=args.steps)}), flush=True)
+        return
+    if args.drops_only:
+        print(json.dumps({"drops": run_drops()}), flush=True)
         return
     if args.batch_only:
         launch = (tile[0], tile[1], args.blocks_per_cu, False) if tile else None
@@ -272,6 +308,11 @@ def main():
                                  "outlet_ms": round(ktb[2], 4),
                                  "intact_length_range": [min(lb), max(lb)]}
         print(f"[bench] batched_fp16 {forms['batched_fp16']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+
+    if not args.no_drops:
+        forms["drops"] = run_drops()
+        print(f"[bench] drops {forms['drops']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
     if not args.no_surrogate:

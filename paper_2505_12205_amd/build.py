@@ -1,6 +1,7 @@
 """Build the HIP C-ABI libraries for gfx950 with hipcc, in-tree:
-liblbm.so (the phase-field LBM step, include/lbm.h) and libsurr.so (the
-learned surrogate's kernels, include/surrogate.h)."""
+liblbm.so (the phase-field LBM step, include/lbm.h), libsurr.so (the
+learned surrogate's kernels, include/surrogate.h) and libdrops.so (the
+drop-size diagnostic, include/drops.h)."""
 from __future__ import annotations
 
 import os
@@ -13,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
 SURR_LIB = os.path.join(LIBDIR, "libsurr.so")
-TARGETS = [(LIB, ["lbm.hip"]), (SURR_LIB, ["nn.hip"])]
+DROPS_LIB = os.path.join(LIBDIR, "libdrops.so")
+TARGETS = [(LIB, ["lbm.hip"]), (SURR_LIB, ["nn.hip"]), (DROPS_LIB, ["ccl.hip"])]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
@@ -33,7 +35,7 @@ def _compile(out: str, sources, verbose: bool):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile both libraries (in parallel); returns the LBM library path."""
+    """Compile the libraries (in parallel); returns the LBM library path."""
     os.makedirs(LIBDIR, exist_ok=True)
     procs = [_compile(out, srcs, verbose) for out, srcs in TARGETS]
     failed = [out for p, out in procs if p.wait() != 0]

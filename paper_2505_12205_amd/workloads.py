@@ -186,6 +186,40 @@ def jet_sweep(n=64, nx=96, ny=96, radius=8.0, reynolds=200.0, lengths=None, webe
     return out
 
 
+def breakup_field(nx=192, ny=192, nz=768, radius=12.0, intact=300.0, xi=4.0, seed=7, ndrops=None):
+    """A phase field with the structure of a breaking jet, for the drop
+    diagnostic: an intact liquid column of the nozzle radius from the inlet
+    plane (z = 0) to z = intact, then a train of separated spherical drops
+    (radii 0.4 R to 1.4 R, lateral offsets up to R/2) and small satellites
+    (radius 2 to 3) towards the outlet, every interface with the tanh
+    profile of width xi (a drop's profile is evaluated within 4 xi of its
+    surface).  Returns (phi [nz, ny, nx] float32, drops), drops a list of
+    (centre (x, y, z), radius) of every sphere placed."""
+    rng = np.random.default_rng(seed)
+    cx, cy = nx / 2.0, ny / 2.0
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((xx - cx) ** 2 + (yy - cy) ** 2)
+    zz = np.arange(nz)
+    phi = (_tanh_profile(intact - zz, xi)[:, None, None] * _tanh_profile(radius - r, xi)[None]).astype(np.float32)
+    drops = []
+    zc = intact + 2.0 * radius
+    while zc < nz - 2.5 * radius and (ndrops is None or len(drops) < ndrops):
+        big = len(drops) % 3 != 2
+        rd = radius * rng.uniform(0.4, 1.4) if big else rng.uniform(2.0, 3.0)
+        c = (cx + rng.uniform(-0.5, 0.5) * radius, cy + rng.uniform(-0.5, 0.5) * radius, zc + rd)
+        m = rd + 4.0 * xi
+        lo = [max(0, int(np.floor(c[d] - m))) for d in range(3)]
+        hi = [min(n, int(np.ceil(c[d] + m)) + 1) for d, n in enumerate((nx, ny, nz))]
+        z, y, x = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]), np.arange(lo[0], hi[0]),
+                              indexing="ij")
+        d = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        box = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        phi[box] = np.maximum(phi[box], _tanh_profile(rd - d, xi))
+        drops.append((c, rd))
+        zc = c[2] + rd + xi + 3.0  # a gap of more than one interface width
+    return phi, drops
+
+
 def phi_in_profile(cfg):
     """Nozzle profile psi(r) on the inlet face (for diagnostics)."""
     x, y, _ = _grid(cfg["nx"], cfg["ny"], 1)

@@ -88,6 +88,26 @@ def test_surrogate_rejects_bad_sizes_on_host():
     assert nn.lib.sg_conv3d_bwd_weight_workspace(2, 8, 8, 8, 16, 32, 2, 1) > 0
 
 
+def test_drops_library_exports_every_declared_symbol_and_rejects_on_host():
+    from paper_2505_12205_amd import drops
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "drops.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(dr_[a-z_0-9]+)\s*\(", txt)))
+    assert "dr_label" in names and "dr_components" in names
+    for n in names:
+        assert hasattr(drops.lib, n), n
+    assert set(names) == set(drops.EXPORTED)
+    # extents and arguments are checked before any device call
+    assert drops.lib.dr_workspace_bytes(0, 4, 4) == 0
+    assert drops.lib.dr_workspace_bytes(2048, 1024, 1024) == 0  # beyond 2^30 nodes
+    n = drops.lib.dr_workspace_bytes(70, 5, 4)
+    assert n >= 4 * 70 * 5 * 4
+    assert drops.lib.dr_label(None, 70, 5, 4, 0, 0.5, None, None, n, None) == drops.DR_EINVAL
+    assert drops.lib.dr_label(1, 70, 5, 4, 8, 0.5, 1, 1, n, None) == drops.DR_EINVAL  # bad periodic bits
+    assert drops.lib.dr_label(1, 70, 5, 4, 0, 0.5, 1, 1, n - 1, None) == drops.DR_EINVAL  # small workspace
+    nc = C.c_int()
+    assert drops.lib.dr_components(1, 70, 5, 4, 3, 8, 1, 1, 1, 1, 1, C.byref(nc), 1, n, None) == drops.DR_EINVAL
+
+
 def test_batch_layout_and_validation_on_host():
     """lbm_batch_state_bytes: the sum of the domains' 256-byte aligned
     layouts; batches of mixed lattice or storage, and empty ones, are
