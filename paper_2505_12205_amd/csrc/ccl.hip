@@ -11,8 +11,8 @@
 //             the pair are not both liquid, so each pair of overlapping runs
 //             is joined once, at the start of its overlap;
 //   k_flatten every liquid node takes its root.
-// Statistics: the roots are compacted in ascending order (per-block counts,
-// one scan, ordered writes), then every run of equal labels within a wave
+// Statistics: the roots are compacted in ascending order (counts per chunk
+// of 4096 nodes, one scan, ordered writes), then every run of equal labels within a wave
 // adds its length and extent with one set of atomics.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,6 +39,8 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 constexpr int TPB = 256;
+constexpr int SLABS = 16;              // 256-node slabs per compaction block
+constexpr int CHUNK = TPB * SLABS;     // nodes per compaction block
 constexpr int UNION_CAP = 1 << 20;  // retries of one union; hitting it flags an error
 constexpr int FIND_CAP = 1 << 26;   // steps of one root search (a chain strictly decreases)
 
@@ -142,10 +144,13 @@ __global__ __launch_bounds__(TPB) void k_flatten(Ext e, int* L, int* flag) {
   __hip_atomic_store(L + i, find_root(L, l, flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// roots per block
+// roots per chunk of CHUNK nodes
 __global__ __launch_bounds__(TPB) void k_root_count(const int* __restrict__ L, Ext e, int* __restrict__ cnt) {
-  const int i = blockIdx.x * TPB + threadIdx.x;
-  const int r = __syncthreads_count(i < e.N && L[i] == i);
+  int r = 0;
+  for (int s = 0; s < SLABS; ++s) {
+    const int i = blockIdx.x * CHUNK + s * TPB + threadIdx.x;
+    r += __syncthreads_count(i < e.N && L[i] == i);
+  }
   if (threadIdx.x == 0) cnt[blockIdx.x] = r;
 }
 
@@ -172,28 +177,36 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ cnt, int 
   if (threadIdx.x == 0) *ncomp = carry;
 }
 
-// component index of every root, in ascending node order; initialise the outputs
+// component index of every root, in ascending node order (the chunk's
+// offset, then slab by slab); initialise the outputs
 __global__ __launch_bounds__(TPB) void k_root_write(const int* __restrict__ L, Ext e, const int* __restrict__ off,
                                                     int cap, int* __restrict__ cid, int* __restrict__ root,
                                                     int* __restrict__ size, int* __restrict__ lo,
                                                     int* __restrict__ hi) {
   __shared__ int wcount[TPB / 64];
-  const int i = blockIdx.x * TPB + threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const bool isroot = i < e.N && L[i] == i;
-  const uint64_t m = __ballot(isroot);
-  if (lane == 0) wcount[wv] = __popcll(m);
-  __syncthreads();
-  if (!isroot) return;
-  int rank = __popcll(m & (lanes_upto(lane) >> 1));
-  for (int w = 0; w < wv; ++w) rank += wcount[w];
-  const int k = off[blockIdx.x] + rank;
-  cid[i] = k;
-  if (k < cap) {
-    root[k] = i;
-    size[k] = 0;
-    lo[k] = INT_MAX;
-    hi[k] = -1;
+  int base = off[blockIdx.x];
+  for (int s = 0; s < SLABS; ++s) {
+    const int i = blockIdx.x * CHUNK + s * TPB + threadIdx.x;
+    const bool isroot = i < e.N && L[i] == i;
+    const uint64_t m = __ballot(isroot);
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int rank = __popcll(m & (lanes_upto(lane) >> 1));
+    for (int w = 0; w < wv; ++w) rank += wcount[w];
+    const int slab_total = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    if (isroot) {
+      const int k = base + rank;
+      cid[i] = k;
+      if (k < cap) {
+        root[k] = i;
+        size[k] = 0;
+        lo[k] = INT_MAX;
+        hi[k] = -1;
+      }
+    }
+    base += slab_total;
+    __syncthreads();  // wcount is rewritten by the next slab
   }
 }
 
@@ -236,7 +249,7 @@ __global__ void k_deq(const int* __restrict__ ncomp, int cap, bool three_d, cons
 
 struct WsLayout {
   size_t flag, ncomp, cnt, off, cid, total;
-  int nblk;
+  int nblk, nchunk;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -247,11 +260,12 @@ bool layout_of(int nx, int ny, int nz, WsLayout& w) {
   if (n > (double)(1 << 30)) return false;
   const int N = nx * ny * nz;
   w.nblk = (N + TPB - 1) / TPB;
+  w.nchunk = (N + CHUNK - 1) / CHUNK;
   w.flag = 0;
   w.ncomp = sizeof(int);
   w.cnt = 256;
-  w.off = w.cnt + align256(sizeof(int) * (size_t)w.nblk);
-  w.cid = w.off + align256(sizeof(int) * (size_t)w.nblk);
+  w.off = w.cnt + align256(sizeof(int) * (size_t)w.nchunk);
+  w.cid = w.off + align256(sizeof(int) * (size_t)w.nchunk);
   w.total = w.cid + align256(sizeof(int) * (size_t)N);
   return true;
 }
@@ -305,9 +319,10 @@ int dr_components(const int* label, int nx, int ny, int nz, int axis, int cap, i
   int* off = (int*)(base + w.off);
   int* cid = (int*)(base + w.cid);
   const Ext e{nx, ny, nz, nx * ny * nz};
-  hipLaunchKernelGGL(k_root_count, dim3(w.nblk), dim3(TPB), 0, st, label, e, cnt);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, w.nblk, off, nc);
-  hipLaunchKernelGGL(k_root_write, dim3(w.nblk), dim3(TPB), 0, st, label, e, off, cap, cid, root, size, lo, hi);
+  hipLaunchKernelGGL(k_root_count, dim3(w.nchunk), dim3(TPB), 0, st, label, e, cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, w.nchunk, off, nc);
+  hipLaunchKernelGGL(k_root_write, dim3(w.nchunk), dim3(TPB), 0, st, label, e, off, cap, cid, root, size, lo,
+                     hi);
   hipLaunchKernelGGL(k_accumulate, dim3(w.nblk), dim3(TPB), 0, st, label, e, axis, cid, cap, size, lo, hi);
   if (cap > 0)
     hipLaunchKernelGGL(k_deq, dim3((cap + 255) / 256), dim3(256), 0, st, nc, cap, nz > 1, size, deq);
