@@ -207,7 +207,8 @@ int lbm_batch_init(int ndom, const lbm_params* per_domain, const float* const* p
                    lbm_batch** out);
 int lbm_batch_step(lbm_batch* b, int n);
 long long lbm_batch_steps_done(const lbm_batch* b);
-/* mass[ndom], kinetic[ndom] (host); FP64, fixed order; synchronises */
+/* mass[ndom], kinetic[ndom] (host); FP64, fixed order; synchronises.  Every
+ * entry is written; LBM_EUNSTABLE if any domain's value is not finite. */
 int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic);
 int lbm_batch_fields(lbm_batch* b, int dom, unsigned mask, float* phi_dev, float* u_dev, float* p_dev);
 int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, float* u_dev);

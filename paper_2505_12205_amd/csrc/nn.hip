@@ -912,9 +912,203 @@ void launch_halo(int n, int d, int h, int w, int c, const uint16_t* x, const uin
   else launch_halo_c<32, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
 }
 
+// ---------------------------------------------------------------------------
+// weight gradient of stride-1 layers from LDS halo bricks
+// ---------------------------------------------------------------------------
+// A block walks output bricks of TZ x TY rows of 16 voxels.  Per brick it
+// stages dz transposed (channel-major, dzT[o][row][x]) and the input with a
+// one-voxel halo transposed (xT[c][hz][hy][hx], in upsampled coordinates for
+// U = 2), once.  Wave w owns the nine taps with kz = w: per 32-voxel K step
+// it reads the dz operand once and, for each ky, one halo row segment
+// (two aligned 16-byte reads) from which the three kx shifts are cut with
+// byte alignment -- dW[o][tap][c] += dz[p][o] X[p + tap - 1][c].  The
+// per-block sums go to the same partial layout as the direct kernels.
+template <int CO, int CI>
+struct WHalo {
+  static constexpr int NO = CO / 16, NC = CI / 16;
+  static constexpr int TZ = CI == 16 ? 4 : 2, TY = (CI == 32 && CO == 32) ? 4 : 8;
+  static constexpr int R = TZ * TY;                 // rows of 16 voxels
+  static constexpr int HX = 18, HXP = 24, HY = TY + 2, HZ = TZ + 2;
+  static constexpr int DZS = R * 16 + 8;            // dzT channel stride (elements), 4 banks apart
+  static constexpr int XB = HZ * HY * HXP;          // halo elements per channel
+  static constexpr int XCS = XB + 2 * ((20 - (XB / 2) % 64 + 64) % 64);  // 20 banks apart
+  static constexpr int DZ_ELEMS = CO * DZS, X_ELEMS = CI * XCS;
+};
+constexpr int kWHaloBlocks = 1024;
+
+struct WGeo {
+  int n, d, h, w;     // layer input extent
+  int od, oh, ow;     // output extent (= U x input)
+  int ntx, nty, ntz;  // bricks along x, y, z
+  int nbricks;
+};
+
+__device__ __forceinline__ v8bf as_bf8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint4 v = {a, b, c, d};
+  return __builtin_bit_cast(v8bf, v);
+}
+
+template <int CO, int CI, int U>
+__global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restrict__ x,
+                                                         const uint16_t* __restrict__ dz, WGeo g,
+                                                         float* __restrict__ part, float* __restrict__ dbpart) {
+  using T = WHalo<CO, CI>;
+  constexpr int NO = T::NO, NC = T::NC, TZ = T::TZ, TY = T::TY, R = T::R;
+  constexpr int HX = T::HX, HXP = T::HXP, HY = T::HY, HZ = T::HZ, DZS = T::DZS, XCS = T::XCS;
+  __shared__ __attribute__((aligned(16))) uint16_t dzT[T::DZ_ELEMS];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[T::X_ELEMS];
+  const int lane = threadIdx.x & 63, kz = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  v4f acc[9][NO * NC], accb[NO];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int i = 0; i < NO * NC; ++i) acc[t][i] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < NO; ++i) accb[i] = (v4f){0.f, 0.f, 0.f, 0.f};
+  v8bf ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.0f;
+  for (int b = blockIdx.x; b < g.nbricks; b += gridDim.x) {
+    int r0 = b;
+    const int tx = r0 % g.ntx;
+    r0 /= g.ntx;
+    const int ty = r0 % g.nty;
+    r0 /= g.nty;
+    const int tz = r0 % g.ntz;
+    const int n = r0 / g.ntz;
+    const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
+    __syncthreads();  // the previous brick's reads are done
+    for (int i = threadIdx.x; i < R * 16 * (CO / 8); i += 192) {
+      const int c8 = (i % (CO / 8)) * 8, v = i / (CO / 8);
+      const int gz = z0 + (v >> 4) / TY, gy = y0 + (v >> 4) % TY, gx = x0 + (v & 15);
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (gz < g.od && gy < g.oh && gx < g.ow)
+        val = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * CO + c8);
+      const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dzT[(c8 + j) * DZS + v] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
+    }
+    for (int i = threadIdx.x; i < HZ * HY * HX * (CI / 8); i += 192) {
+      const int c8 = (i % (CI / 8)) * 8, hv = i / (CI / 8);
+      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+      const int qx = x0 - 1 + hx, qy = y0 - 1 + hy, qz = z0 - 1 + hz;
+      uint4 val = {0u, 0u, 0u, 0u};
+      if (qx >= 0 && qx < g.ow && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od)
+        val = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * CI + c8);
+      const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        xT[(c8 + j) * XCS + (hz * HY + hy) * HXP + hx] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
+    }
+    __syncthreads();
+    for (int st = 0; st < R / 2; ++st) {
+      const int r = 2 * st + (quad >> 1), xo = 8 * (quad & 1);
+      const int rz = r / TY, ry = r % TY;
+      v8bf a[NO];
+#pragma unroll
+      for (int ot = 0; ot < NO; ++ot) a[ot] = *(const v8bf*)&dzT[(ot * 16 + col) * DZS + r * 16 + xo];
+      if (kz == 0)
+#pragma unroll
+        for (int ot = 0; ot < NO; ++ot) accb[ot] = mfma32(a[ot], ones, accb[ot]);
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+#pragma unroll
+        for (int ct = 0; ct < NC; ++ct) {
+          const uint16_t* src = &xT[(ct * 16 + col) * XCS + ((rz + kz) * HY + ry + ky) * HXP + xo];
+          const uint4 lo = *(const uint4*)src, hi = *(const uint4*)(src + 8);
+          // window elements kx .. kx + 7 of the 16 read: kx = 1 shifts by one bf16
+          const v8bf b0 = as_bf8(lo.x, lo.y, lo.z, lo.w);
+          const v8bf b1 = as_bf8(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                                 __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi.x, lo.w, 2));
+          const v8bf b2 = as_bf8(lo.y, lo.z, lo.w, hi.x);
+#pragma unroll
+          for (int ot = 0; ot < NO; ++ot) {
+            acc[ky * 3 + 0][ot * NC + ct] = mfma32(a[ot], b0, acc[ky * 3 + 0][ot * NC + ct]);
+            acc[ky * 3 + 1][ot * NC + ct] = mfma32(a[ot], b1, acc[ky * 3 + 1][ot * NC + ct]);
+            acc[ky * 3 + 2][ot * NC + ct] = mfma32(a[ot], b2, acc[ky * 3 + 2][ot * NC + ct]);
+          }
+        }
+      }
+    }
+  }
+  // lane holds D[4 quad + r][col]: o = ot*16 + 4 quad + r, c = ct*16 + col
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int tap = kz * 9 + t;
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int ct = 0; ct < NC; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[(((long long)blockIdx.x * 27 + tap) * CO + ot * 16 + 4 * quad + r) * CI + ct * 16 + col] =
+              acc[t][ot * NC + ct][r];
+  }
+  if (kz == 0 && col == 0)
+#pragma unroll
+    for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dbpart[(long long)blockIdx.x * CO + ot * 16 + 4 * quad + r] = accb[ot][r];
+}
+
 // voxel chunking of the weight gradient: about 2048 blocks (the per-tap
 // kernel has 27 blocks per chunk, the all-taps kernel one)
-void wchunks(const Geo& g, int& nchunk, long long& vchunk) {
+// the halo-brick weight gradient takes stride-1 layers of up to 32 channels
+bool whalo_ok(const Geo& g, int stride) { return stride == 1 && g.co <= 32 && g.ci <= 32; }
+
+template <int CO, int CI>
+WGeo whalo_geo(const Geo& g) {
+  using T = WHalo<CO, CI>;
+  WGeo w;
+  w.n = g.n;
+  w.d = g.d;
+  w.h = g.h;
+  w.w = g.w;
+  w.od = g.od;
+  w.oh = g.oh;
+  w.ow = g.ow;
+  w.ntx = (g.ow + 15) / 16;
+  w.nty = (g.oh + T::TY - 1) / T::TY;
+  w.ntz = (g.od + T::TZ - 1) / T::TZ;
+  w.nbricks = w.ntx * w.nty * w.ntz * g.n;
+  return w;
+}
+
+WGeo whalo_geo_of(const Geo& g) {
+  if (g.ci == 16) return g.co == 16 ? whalo_geo<16, 16>(g) : whalo_geo<32, 16>(g);
+  return g.co == 16 ? whalo_geo<16, 32>(g) : whalo_geo<32, 32>(g);
+}
+
+template <int CO, int CI>
+void launch_whalo_c(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, int nchunk, float* part,
+                    float* dbpart, hipStream_t st) {
+  const WGeo w = whalo_geo<CO, CI>(g);
+  if (up == 1)
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 1>), dim3(nchunk), dim3(192), 0, st, x, dz, w, part, dbpart);
+  else
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 2>), dim3(nchunk), dim3(192), 0, st, x, dz, w, part, dbpart);
+}
+
+void launch_whalo(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, int nchunk, float* part,
+                  float* dbpart, hipStream_t st) {
+  if (g.ci == 16) {
+    if (g.co == 16) launch_whalo_c<16, 16>(g, up, x, dz, nchunk, part, dbpart, st);
+    else launch_whalo_c<32, 16>(g, up, x, dz, nchunk, part, dbpart, st);
+  } else {
+    if (g.co == 16) launch_whalo_c<16, 32>(g, up, x, dz, nchunk, part, dbpart, st);
+    else launch_whalo_c<32, 32>(g, up, x, dz, nchunk, part, dbpart, st);
+  }
+}
+
+void wchunks(const Geo& g, int stride, int& nchunk, long long& vchunk) {
+  if (whalo_ok(g, stride)) {  // one chunk per block of the brick walk
+    const long long nb = whalo_geo_of(g).nbricks;
+    nchunk = (int)(nb < kWHaloBlocks ? nb : kWHaloBlocks);
+    if (nchunk < 1) nchunk = 1;
+    vchunk = 0;
+    return;
+  }
   const bool all_taps = (g.co / 16) * (g.ci / 16) <= kAllTapsMaxTiles;
   const long long target = all_taps ? 2048 : 76;
   long long vc = (g.mo + target - 1) / target;
@@ -980,7 +1174,7 @@ size_t sg_conv3d_bwd_weight_workspace(int n, int d, int h, int w, int ci, int co
   const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
   int nchunk;
   long long vchunk;
-  wchunks(g, nchunk, vchunk);
+  wchunks(g, stride, nchunk, vchunk);
   return (size_t)nchunk * (27 * (size_t)co * ci + co) * sizeof(float);
 }
 
@@ -994,11 +1188,12 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
   const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
   int nchunk;
   long long vchunk;
-  wchunks(g, nchunk, vchunk);
+  wchunks(g, stride, nchunk, vchunk);
   float* part = (float*)ws;
   float* dbpart = part + (size_t)nchunk * 27 * co * ci;
   hipStream_t st = (hipStream_t)stream;
-  if (stride == 1 && up == 1) launch_bwd_w_su<1, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
+  if (whalo_ok(g, stride)) launch_whalo(g, up, x, dz, nchunk, part, dbpart, st);
+  else if (stride == 1 && up == 1) launch_bwd_w_su<1, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   else if (stride == 2) launch_bwd_w_su<2, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   else launch_bwd_w_su<1, 2>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   const int nred = 27 * co * ci;

@@ -38,8 +38,8 @@ def run(steps=9600, start=4800, every=320, storage="fp16", n=64, log=print):
     counts = [[] for _ in range(n)]
     t = start
     while True:
-        mass, _ = b.reduce()
-        alive &= np.isfinite(mass)
+        mass, ke = b.reduce(strict=False)
+        alive &= np.isfinite(mass) & np.isfinite(ke)
         lengths = b.intact_length(0.5)
         for d in range(n):
             if not alive[d]:

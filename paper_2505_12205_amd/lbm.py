@@ -337,10 +337,14 @@ class Batch:
     def steps_done(self) -> int:
         return int(lib.lbm_batch_steps_done(self._h))
 
-    def reduce(self):
+    def reduce(self, strict: bool = True):
+        """(mass[ndom], kinetic[ndom]); strict=False returns non-finite
+        values of diverged domains instead of raising."""
         m = (C.c_double * self.ndom)()
         k = (C.c_double * self.ndom)()
-        _check(lib.lbm_batch_reduce(self._h, m, k))
+        rc = lib.lbm_batch_reduce(self._h, m, k)
+        if rc != LBM_EUNSTABLE or strict:
+            _check(rc)
         return list(m), list(k)
 
     def fields(self, dom: int):

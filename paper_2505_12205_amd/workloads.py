@@ -78,6 +78,41 @@ def drop2d(n=128, radius=25.0, xi=4.0, rho_h=1.0, rho_l=1e-3, visc_ratio=100.0,
 # 3D Rayleigh-Taylor (D3Q19; periodic x/z, no-slip walls in y)
 # --------------------------------------------------------------------------
 
+def laplace3d(n=100, radius=20.0, sigma=0.005, rho_ratio=1000.0, tau=0.5, xi=4.0, mobility=0.02):
+    """Static drop of the stationary-drop test: a heavy sphere of radius R
+    centred in an n^3 periodic box at rest, tau_H = tau_L = tau, the given
+    surface tension and density ratio (the paper's table: n = 100,
+    R = 15 ... 35, sigma = 0.001, 0.005, 0.01, tau = 0.5, xi = 4,
+    rho* = 1000).  The paper does not give the mobility; 0.02 as for the
+    2D drop."""
+    cfg = dict(q=19, nx=n, ny=n, nz=n, rho_h=1.0, rho_l=1.0 / rho_ratio, tau_h=tau, tau_l=tau,
+               sigma=sigma, xi=xi, mobility=mobility, gravity=(0.0, 0.0, 0.0), body_force="rho",
+               bc=("periodic",) * 6, name=f"laplace3d_{n}_R{radius:g}_s{sigma:g}")
+    x, y, z = _grid(n, n, n)
+    c = n / 2.0
+    r = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    return cfg, _tanh_profile(radius - r, xi), None
+
+
+def laplace_pressure_jump(phi, p, xi=4.0):
+    """(Delta p, R) of a centred static drop: the mean pressure inside
+    r < R - 2 xi minus the mean outside r > R + 2 xi, with the radius of the
+    sphere of the drop's volume, R = (3 sum(phi) / (4 pi))^(1/3) (3D) or
+    (sum(phi) / pi)^(1/2) (2D)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    if nz > 1:
+        R = (3.0 * phi.sum() / (4.0 * np.pi)) ** (1.0 / 3.0)
+        x, y, z = _grid(nx, ny, nz)
+        r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2 + (z - nz / 2.0) ** 2)
+    else:
+        R = np.sqrt(phi.sum() / np.pi)
+        x, y, _ = _grid(nx, ny, 1)
+        r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2)
+    return p[r < R - 2 * xi].mean() - p[r > R + 2 * xi].mean(), R
+
+
 def rt_params(lref=256, atwood=0.5, reynolds=3000.0, u0=0.04, visc_ratio=1.0,
               peclet=1000.0, capillary=0.26, xi=5.0):
     """Lattice-unit parameters of the Rayleigh-Taylor case.
