@@ -166,33 +166,35 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 // ---------------------------------------------------------------------------
 // stride-1 convolution from an LDS halo tile (C channels in and out)
 // ---------------------------------------------------------------------------
-// A block owns TZ x TY rows of 16 voxels along x; it stages the input brick
-// with a one-voxel halo in LDS once, and every tap reads a shifted window of
-// it.  MODE 0 is the forward epilogue (bias, relu, the activation before the
-// skip in y2, skip add); MODE 1 is the data gradient of a stride-1 layer:
-// with the flipped weights wf[c][26 - k][o] = w[o][k][c] the gradient is the
-// same convolution of dz, and the epilogue adds `add`, stores the sum in y2
-// and the sum masked by mask > 0 in y.
-template <int C>
+// A block owns TZ x TY rows of 16 output voxels along x; it stages the
+// input brick with a one-voxel halo in LDS once (in upsampled coordinates
+// for U = 2: the halo voxel q holds x[q / 2]), and every tap reads a shifted
+// window of it.  MODE 0 is the forward epilogue (bias, relu, the activation
+// before the skip in y2, skip add); MODE 1 is the data gradient of a stride-1
+// layer (U = 1, CI = CO): with the flipped weights wf[c][26 - k][o] =
+// w[o][k][c] the gradient is the same convolution of dz, and the epilogue
+// adds `add`, stores the sum in y2 and the sum masked by mask > 0 in y.
+template <int CI, int CO>
 struct HaloTile {
-  static constexpr int NS = C / 16, MS = 8 / NS, ROWS = 4 * MS;
+  static constexpr int NS = CO / 16, MS = 8 / NS, ROWS = 4 * MS;
   static constexpr int TY = ROWS >= 16 ? 8 : 4, TZ = ROWS / TY;
   static constexpr int HX = 18, HY = TY + 2, HZ = TZ + 2;
-  static constexpr int ELEMS = HZ * HY * HX * C;
+  static constexpr int ELEMS = HZ * HY * HX * CI;
 };
 
 struct HGeo {
-  int n, d, h, w;          // extent (input = output)
+  int n, d, h, w;          // input extent
+  int od, oh, ow;          // output extent (U x input)
   int ntx, nty, ntz;       // tiles along x, y, z
 };
 
-template <int C, int MODE>
+template <int CI, int CO, int U, int MODE>
 __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ x, const uint16_t* __restrict__ wgt,
                                                    const float* __restrict__ bias,
                                                    const uint16_t* __restrict__ other,
                                                    const uint16_t* __restrict__ mask, uint16_t* __restrict__ y,
                                                    uint16_t* __restrict__ y2, HGeo g, int relu) {
-  using T = HaloTile<C>;
+  using T = HaloTile<CI, CO>;
   constexpr int NS = T::NS, MS = T::MS, TY = T::TY, TZ = T::TZ, HX = T::HX, HY = T::HY, HZ = T::HZ;
   __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS];
   int b = blockIdx.x;
@@ -204,14 +206,14 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   const int n = b / g.ntz;
   const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
   // stage the brick and its halo, zero outside the grid
-  for (int i = threadIdx.x; i < HZ * HY * HX * (C / 8); i += 256) {
-    const int c8 = (i % (C / 8)) * 8, vox = i / (C / 8);
+  for (int i = threadIdx.x; i < HZ * HY * HX * (CI / 8); i += 256) {
+    const int c8 = (i % (CI / 8)) * 8, vox = i / (CI / 8);
     const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
     v8bf val = {};
-    if (gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
-      val = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * C + c8);
-    *(v8bf*)&halo[vox * C + c8] = val;
+    if (gx >= 0 && gx < g.ow && gy >= 0 && gy < g.oh && gz >= 0 && gz < g.od)
+      val = ld8(x + ((((long long)n * g.d + gz / U) * g.h + gy / U) * g.w + gx / U) * CI + c8);
+    *(v8bf*)&halo[vox * CI + c8] = val;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -221,10 +223,10 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   for (int m = 0; m < MS; ++m)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
-  constexpr int K = 27 * C;
-  constexpr int csh = NS == 1 ? 4 : (NS == 2 ? 5 : 6);
+  constexpr int K = 27 * CI;
+  constexpr int csh = CI == 16 ? 4 : (CI == 32 ? 5 : 6);
   for (int k0 = 0; k0 < K; k0 += 32) {
-    const int k = k0 + 8 * quad;  // K is a multiple of 32 for C >= 32, and of 16 for C = 16
+    const int k = k0 + 8 * quad;  // K is a multiple of 32 for CI >= 32, and of 16 for CI = 16
     const bool kin = k < K;
     const int tap = kin ? (k >> csh) : 0, c = k - (tap << csh);
     const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
       const int r = wv * MS + m, rz = r / TY, ry = r % TY;
-      a[m] = kin ? *(const v8bf*)&halo[(((rz + kz) * HY + (ry + ky)) * HX + (col + kx)) * C + c] : (v8bf){};
+      a[m] = kin ? *(const v8bf*)&halo[(((rz + kz) * HY + (ry + ky)) * HX + (col + kx)) * CI + c] : (v8bf){};
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : (v8bf){};
@@ -245,16 +247,16 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
 #pragma unroll
   for (int m = 0; m < MS; ++m) {
     const int rr = wv * MS + m, gz = z0 + rr / TY, gy = y0 + rr % TY;
-    if (gz >= g.d || gy >= g.h) continue;
+    if (gz >= g.od || gy >= g.oh) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gx = x0 + 4 * quad + r;
-      if (gx >= g.w) continue;
-      const long long v = (((long long)n * g.d + gz) * g.h + gy) * g.w + gx;
+      if (gx >= g.ow) continue;
+      const long long v = (((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const int o = s * 16 + col;
-        const long long i = v * C + o;
+        const long long i = v * CO + o;
         float val = acc[m][s][r];
         if (MODE == 0) {
           val += bias[o];
@@ -882,34 +884,43 @@ void launch_bwd_w_su(const Geo& g, const uint16_t* x, const uint16_t* dz, int nc
   else launch_bwd_w_co<64, S, U>(g, x, dz, nchunk, vchunk, part, dbpart, st);
 }
 
-template <int C, int MODE>
+template <int CI, int CO, int U, int MODE>
 void launch_halo_c(int n, int d, int h, int w, const uint16_t* x, const uint16_t* wgt, const float* bias,
                    const uint16_t* other, const uint16_t* mask, uint16_t* y, uint16_t* y2, int relu, hipStream_t st) {
-  using T = HaloTile<C>;
+  using T = HaloTile<CI, CO>;
   HGeo g;
   g.n = n;
   g.d = d;
   g.h = h;
   g.w = w;
-  g.ntx = (w + 15) / 16;
-  g.nty = (h + T::TY - 1) / T::TY;
-  g.ntz = (d + T::TZ - 1) / T::TZ;
+  g.od = U * d;
+  g.oh = U * h;
+  g.ow = U * w;
+  g.ntx = (g.ow + 15) / 16;
+  g.nty = (g.oh + T::TY - 1) / T::TY;
+  g.ntz = (g.od + T::TZ - 1) / T::TZ;
   const long long blocks = (long long)g.ntx * g.nty * g.ntz * n;
-  hipLaunchKernelGGL((k_conv_halo<C, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, x, wgt, bias, other, mask, y,
-                     y2, g, relu);
+  hipLaunchKernelGGL((k_conv_halo<CI, CO, U, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, x, wgt, bias, other,
+                     mask, y, y2, g, relu);
 }
 
 // The halo tile pays where the layer is narrow: at 64 channels a block holds
 // only 8 rows and stages 3.4x its own voxels, and the direct kernel is faster
 // (measured per layer width; the data gradient gains at 16 channels only).
-bool halo_fwd(int c) { return c <= 32; }
+// Upsampling layers gain where the output is narrow: the 32 -> 16 channel
+// layer at full resolution (its halo is 69 KB of LDS).
+bool halo_fwd(int ci, int co, int stride, int up) {
+  if (stride != 1) return false;
+  if (up == 1) return ci == co && co <= 32;
+  return ci == 32 && co == 16;
+}
 bool halo_data(int c) { return c == 16; }
 
 template <int MODE>
 void launch_halo(int n, int d, int h, int w, int c, const uint16_t* x, const uint16_t* wgt, const float* bias,
                  const uint16_t* other, const uint16_t* mask, uint16_t* y, uint16_t* y2, int relu, hipStream_t st) {
-  if (c == 16) launch_halo_c<16, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
-  else launch_halo_c<32, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
+  if (c == 16) launch_halo_c<16, 16, 1, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
+  else launch_halo_c<32, 32, 1, MODE>(n, d, h, w, x, wgt, bias, other, mask, y, y2, relu, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1141,8 +1152,11 @@ int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const u
   if (!x || !wgt || !bias || !y) return fail(SG_EINVAL, "null tensor");
   const Geo g = make_geo(n, d, h, w, ci, co, stride, up);
   hipStream_t st = (hipStream_t)stream;
-  if (stride == 1 && up == 1 && ci == co && halo_fwd(co)) {
-    launch_halo<0>(n, d, h, w, co, x, wgt, bias, skip, nullptr, y, yr, relu, st);
+  if (halo_fwd(ci, co, stride, up)) {
+    if (up == 1)
+      launch_halo<0>(n, d, h, w, co, x, wgt, bias, skip, nullptr, y, yr, relu, st);
+    else
+      launch_halo_c<32, 16, 2, 0>(n, d, h, w, x, wgt, bias, skip, nullptr, y, yr, relu, st);
     return check_launch("sg_conv3d_fwd");
   }
   if (stride == 1 && up == 1) launch_fwd_su<1, 1>(g, x, wgt, bias, skip, y, yr, relu, st);
