@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -667,13 +668,24 @@ __global__ void k_normalize(const float* __restrict__ x, int c, long long vox, l
   xn[i] = (x[i] - shift[ch]) * scale[ch];
 }
 
-__global__ void k_pack(const float* __restrict__ xn, int c, long long vox, int cpad, long long total,
+// one thread per voxel: its c channels (coalesced over voxels per channel),
+// written as cpad bf16 with 16-byte stores
+__global__ void k_pack(const float* __restrict__ xn, int c, long long vox, int cpad, long long nvox,
                        uint16_t* __restrict__ xb) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][vox][cpad]
-  if (i >= total) return;
-  const int ch = (int)(i % cpad);
-  const long long v = (i / cpad) % vox, n = i / (cpad * vox);
-  xb[i] = ch < c ? f2bf(xn[(n * c + ch) * vox + v]) : (uint16_t)0;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // over [n][vox]
+  if (q >= nvox) return;
+  const long long n = q / vox, v = q - n * vox;
+  for (int c0 = 0; c0 < cpad; c0 += 8) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int ch = c0 + 2 * j;
+      const uint32_t lo = ch < c ? f2bf(xn[(n * c + ch) * vox + v]) : 0u;
+      const uint32_t hi = ch + 1 < c ? f2bf(xn[(n * c + ch + 1) * vox + v]) : 0u;
+      w[j] = lo | (hi << 16);
+    }
+    *(uint4*)(xb + q * cpad + c0) = (uint4){w[0], w[1], w[2], w[3]};
+  }
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -691,47 +703,71 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 constexpr int kLossBlocks = 1024;
 constexpr int kLossMaxSamples = 1024;  // mass term: per-sample sums follow the partials in ws
 
-// per-sample sum of the phase-field residual d = xn + rs r - tn (channel 0),
-// FP64, one block per sample (fixed order)
+// per-sample sums of the phase-field residual d = xn + rs r - tn (channel 0),
+// FP64: blockIdx.y = sample, blockIdx.x = one of np partial ranges, then
+// k_mass_final adds the np partials of each sample in a fixed order
 __global__ __launch_bounds__(256) void k_mass_residual(const float* __restrict__ xn, const float* __restrict__ tn,
                                                        const uint16_t* __restrict__ r,
                                                        const float* __restrict__ rs, int c, long long vox,
-                                                       int cpad, double* __restrict__ msum) {
+                                                       int cpad, int np, double* __restrict__ mpart) {
   __shared__ double sh[4];
-  const long long n = blockIdx.x;
+  const long long n = blockIdx.y;
   const float sc = rs ? rs[0] : 1.0f;
   double s = 0.0;
-  for (long long v = threadIdx.x; v < vox; v += blockDim.x) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < vox; v += (long long)np * blockDim.x) {
     const long long j = n * c * vox + v;
     s += (double)(xn[j] + sc * bf2f(r[(n * vox + v) * cpad]) - tn[j]);
   }
   const double b = block_sum(s, sh);
-  if (threadIdx.x == 0) msum[n] = b;
+  if (threadIdx.x == 0) mpart[n * np + blockIdx.x] = b;
 }
 
+__global__ void k_mass_final(const double* __restrict__ mpart, int n, int np, double* __restrict__ msum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < np; ++k) s += mpart[(long long)i * np + k];
+  msum[i] = s;
+}
+
+// one thread per voxel (grid-stride): its cpad residual channels read and
+// its gradient written with 16-byte accesses, the c real channels' d^2
+// accumulated in FP64; per-block partials in a fixed order
 __global__ __launch_bounds__(256) void k_residual_loss(const float* __restrict__ xn, const float* __restrict__ tn,
                                                        const uint16_t* __restrict__ r,
                                                        const float* __restrict__ rs, int c, long long vox,
-                                                       int cpad, long long total, float inv_count,
+                                                       int cpad, long long nvox, float inv_count,
                                                        const double* __restrict__ msum, float mgrad,
                                                        uint16_t* __restrict__ dr, double* __restrict__ part) {
   __shared__ double sh[4];
   double s = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {  // over [n][vox][cpad]
-    const int ch = (int)(i % cpad);
-    float gval = 0.0f;
-    if (ch < c) {
-      const long long v = (i / cpad) % vox, n = i / (cpad * vox);
-      const long long j = (n * c + ch) * vox + v;
-      const float sc = rs ? rs[ch] : 1.0f;
-      const float d = xn[j] + sc * bf2f(r[i]) - tn[j];
-      s += (double)d * d;
-      float gd = 2.0f * d * inv_count;
-      if (msum && ch == 0) gd += mgrad * (float)msum[n];  // d/dd of the mass term
-      gval = sc * gd;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nvox;
+       q += (long long)gridDim.x * blockDim.x) {  // over [n][vox]
+    const long long n = q / vox, v = q - n * vox;
+    const float mg = msum ? mgrad * (float)msum[n] : 0.0f;  // d/dd of the mass term (channel 0)
+    for (int c0 = 0; c0 < cpad; c0 += 8) {
+      const uint4 rv = *(const uint4*)(r + q * cpad + c0);
+      const uint32_t rw[4] = {rv.x, rv.y, rv.z, rv.w};
+      uint32_t gw[4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int ch = c0 + j;
+        float gval = 0.0f;
+        if (ch < c) {
+          const long long jx = (n * c + ch) * vox + v;
+          const float sc = rs ? rs[ch] : 1.0f;
+          const float d = xn[jx] + sc * bf2f((uint16_t)(rw[j >> 1] >> (16 * (j & 1)))) - tn[jx];
+          s += (double)d * d;
+          float gd = 2.0f * d * inv_count;
+          if (ch == 0) gd += mg;
+          gval = sc * gd;
+        }
+        const uint32_t b = f2bf(gval);
+        if (j & 1) gw[j >> 1] |= b << 16;
+        else gw[j >> 1] = b;
+      }
+      *(uint4*)(dr + q * cpad + c0) = (uint4){gw[0], gw[1], gw[2], gw[3]};
     }
-    dr[i] = f2bf(gval);
   }
   const double b = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = b;
@@ -1245,9 +1281,9 @@ int sg_normalize(const float* x, int n, int c, long long vox, const float* shift
 
 int sg_pack(const float* xn, int n, int c, long long vox, int cpad, uint16_t* xb, void* stream) {
   if (!xn || !xb || n < 1 || c < 1 || vox < 1 || !chan_ok(cpad) || cpad < c) return fail(SG_EINVAL, "bad pack");
-  const long long total = (long long)n * vox * cpad;
-  hipLaunchKernelGGL(k_pack, dim3(blocks_for(total, 256)), dim3(256), 0, (hipStream_t)stream, xn, c, vox, cpad,
-                     total, xb);
+  const long long nvox = (long long)n * vox;
+  hipLaunchKernelGGL(k_pack, dim3(blocks_for(nvox, 256)), dim3(256), 0, (hipStream_t)stream, xn, c, vox, cpad,
+                     nvox, xb);
   return check_launch("sg_pack");
 }
 
@@ -1258,16 +1294,19 @@ int sg_residual_loss(const float* xn, const float* tn, const uint16_t* r, const 
       !(mass_weight >= 0.0f))
     return fail(SG_EINVAL, "bad loss arguments");
   if (mass_weight > 0.0f && n > kLossMaxSamples) return fail(SG_EINVAL, "mass term: too many samples");
-  const long long total = (long long)n * vox * cpad;
+  const long long nvox = (long long)n * vox;
   const double count = (double)n * c * vox;
   hipStream_t st = (hipStream_t)stream;
   double* part = (double*)ws;
   double* msum = mass_weight > 0.0f ? part + kLossBlocks : nullptr;
-  if (msum)
-    hipLaunchKernelGGL(k_mass_residual, dim3(n), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, msum);
+  if (msum) {  // the mass partials use the loss-partials region before the loss kernel fills it
+    const int np = std::min(64, std::max(1, kLossBlocks / n));
+    hipLaunchKernelGGL(k_mass_residual, dim3(np, n), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, np, part);
+    hipLaunchKernelGGL(k_mass_final, dim3((n + 63) / 64), dim3(64), 0, st, part, n, np, msum);
+  }
   // d/dd of mw * mean_n (S_n / V)^2 is 2 mw S_n / (n V^2)
   const float mgrad = (float)(2.0 * mass_weight / ((double)n * (double)vox * (double)vox));
-  hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, total,
+  hipLaunchKernelGGL(k_residual_loss, dim3(kLossBlocks), dim3(256), 0, st, xn, tn, r, rs, c, vox, cpad, nvox,
                      (float)(1.0 / count), msum, mgrad, dr, part);
   if (loss)
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kLossBlocks, 1.0 / count, msum, n,
