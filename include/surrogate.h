@@ -45,8 +45,8 @@ const char* sg_last_error(void);
  *   yr   : nullable, receives max(z, 0) (or z) before the skip is added
  *          (the gradient needs the activation's own sign).
  * stride 2 with up 2 is rejected.  Stride-1 layers with ci == co <= 32,
- * and the 32 -> 16 channel upsampling layer, stage each block's input brick
- * with its halo in LDS. */
+ * and the 32 -> 16 and 64 -> 32 channel upsampling layers, stage each
+ * block's input brick with its halo in LDS. */
 int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* wgt,
                   const float* bias, int co, int stride, int up, int relu, const uint16_t* skip,
                   uint16_t* y, uint16_t* yr, void* stream);

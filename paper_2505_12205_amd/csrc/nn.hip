@@ -168,18 +168,19 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 // stride-1 convolution from an LDS halo tile (C channels in and out)
 // ---------------------------------------------------------------------------
 // A block owns TZ x TY rows of 16 output voxels along x; it stages the
-// input brick with a one-voxel halo in LDS once (in upsampled coordinates
-// for U = 2: the halo voxel q holds x[q / 2]), and every tap reads a shifted
-// window of it.  MODE 0 is the forward epilogue (bias, relu, the activation
+// input brick with a one-voxel halo in LDS once, and every tap reads a
+// shifted window of it.  With nearest upsampling (U = 2) the brick is staged
+// at the input's resolution, (TZ/2 + 2) x (TY/2 + 2) x 10 voxels, and the
+// tap at virtual position q reads staged voxel floor(q / 2).  MODE 0 is the forward epilogue (bias, relu, the activation
 // before the skip in y2, skip add); MODE 1 is the data gradient of a stride-1
 // layer (U = 1, CI = CO): with the flipped weights wf[c][26 - k][o] =
 // w[o][k][c] the gradient is the same convolution of dz, and the epilogue
 // adds `add`, stores the sum in y2 and the sum masked by mask > 0 in y.
-template <int CI, int CO>
+template <int CI, int CO, int U>
 struct HaloTile {
   static constexpr int NS = CO / 16, MS = 8 / NS, ROWS = 4 * MS;
   static constexpr int TY = ROWS >= 16 ? 8 : 4, TZ = ROWS / TY;
-  static constexpr int HX = 18, HY = TY + 2, HZ = TZ + 2;
+  static constexpr int HX = U == 1 ? 18 : 10, HY = U == 1 ? TY + 2 : TY / 2 + 2, HZ = U == 1 ? TZ + 2 : TZ / 2 + 2;
   static constexpr int ELEMS = HZ * HY * HX * CI;
 };
 
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
                                                    const uint16_t* __restrict__ other,
                                                    const uint16_t* __restrict__ mask, uint16_t* __restrict__ y,
                                                    uint16_t* __restrict__ y2, HGeo g, int relu) {
-  using T = HaloTile<CI, CO>;
+  using T = HaloTile<CI, CO, U>;
   constexpr int NS = T::NS, MS = T::MS, TY = T::TY, TZ = T::TZ, HX = T::HX, HY = T::HY, HZ = T::HZ;
   __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS];
   int b = blockIdx.x;
@@ -206,14 +207,15 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   const int tz = b % g.ntz;
   const int n = b / g.ntz;
   const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
-  // stage the brick and its halo, zero outside the grid
+  // stage the brick and its halo, zero outside the grid; the staged origin
+  // is one input voxel before the brick (x0, y0, z0 are even for U = 2)
   for (int i = threadIdx.x; i < HZ * HY * HX * (CI / 8); i += 256) {
     const int c8 = (i % (CI / 8)) * 8, vox = i / (CI / 8);
     const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    const int gx = x0 / U - 1 + hx, gy = y0 / U - 1 + hy, gz = z0 / U - 1 + hz;
     v8bf val = {};
-    if (gx >= 0 && gx < g.ow && gy >= 0 && gy < g.oh && gz >= 0 && gz < g.od)
-      val = ld8(x + ((((long long)n * g.d + gz / U) * g.h + gy / U) * g.w + gx / U) * CI + c8);
+    if (gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
+      val = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * CI + c8);
     *(v8bf*)&halo[vox * CI + c8] = val;
   }
   __syncthreads();
@@ -235,7 +237,11 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
       const int r = wv * MS + m, rz = r / TY, ry = r % TY;
-      a[m] = kin ? *(const v8bf*)&halo[(((rz + kz) * HY + (ry + ky)) * HX + (col + kx)) * CI + c] : (v8bf){};
+      // staged voxel of virtual offset t = row/col + tap - 1: t + 1 (U = 1), floor(t / 2) + 1 (U = 2)
+      const int lz = U == 1 ? rz + kz : ((rz + kz - 1) >> 1) + 1;
+      const int ly = U == 1 ? ry + ky : ((ry + ky - 1) >> 1) + 1;
+      const int lx = U == 1 ? col + kx : ((col + kx - 1) >> 1) + 1;
+      a[m] = kin ? *(const v8bf*)&halo[((lz * HY + ly) * HX + lx) * CI + c] : (v8bf){};
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : (v8bf){};
@@ -923,7 +929,7 @@ void launch_bwd_w_su(const Geo& g, const uint16_t* x, const uint16_t* dz, int nc
 template <int CI, int CO, int U, int MODE>
 void launch_halo_c(int n, int d, int h, int w, const uint16_t* x, const uint16_t* wgt, const float* bias,
                    const uint16_t* other, const uint16_t* mask, uint16_t* y, uint16_t* y2, int relu, hipStream_t st) {
-  using T = HaloTile<CI, CO>;
+  using T = HaloTile<CI, CO, U>;
   HGeo g;
   g.n = n;
   g.d = d;
@@ -943,12 +949,11 @@ void launch_halo_c(int n, int d, int h, int w, const uint16_t* x, const uint16_t
 // The halo tile pays where the layer is narrow: at 64 channels a block holds
 // only 8 rows and stages 3.4x its own voxels, and the direct kernel is faster
 // (measured per layer width; the data gradient gains at 16 channels only).
-// Upsampling layers gain where the output is narrow: the 32 -> 16 channel
-// layer at full resolution (its halo is 69 KB of LDS).
+// The upsampling layers of the decoder (32 -> 16 and 64 -> 32 channels).
 bool halo_fwd(int ci, int co, int stride, int up) {
   if (stride != 1) return false;
   if (up == 1) return ci == co && co <= 32;
-  return ci == 32 && co == 16;
+  return (ci == 32 && co == 16) || (ci == 64 && co == 32);
 }
 bool halo_data(int c) { return c == 16; }
 
@@ -1191,8 +1196,10 @@ int sg_conv3d_fwd(const uint16_t* x, int n, int d, int h, int w, int ci, const u
   if (halo_fwd(ci, co, stride, up)) {
     if (up == 1)
       launch_halo<0>(n, d, h, w, co, x, wgt, bias, skip, nullptr, y, yr, relu, st);
-    else
+    else if (co == 16)
       launch_halo_c<32, 16, 2, 0>(n, d, h, w, x, wgt, bias, skip, nullptr, y, yr, relu, st);
+    else
+      launch_halo_c<64, 32, 2, 0>(n, d, h, w, x, wgt, bias, skip, nullptr, y, yr, relu, st);
     return check_launch("sg_conv3d_fwd");
   }
   if (stride == 1 && up == 1) launch_fwd_su<1, 1>(g, x, wgt, bias, skip, y, yr, relu, st);

@@ -80,8 +80,8 @@ CASES = [  # (ci, co, stride, up, n, d, h, w)
     # every (co, ci, upsample) of the halo-brick weight gradient
     (16, 16, 1, 2, 1, 3, 5, 10), (32, 32, 1, 2, 1, 3, 5, 9), (16, 32, 1, 1, 1, 6, 9, 21),
     (32, 16, 1, 1, 2, 7, 12, 20), (16, 32, 1, 2, 1, 4, 3, 9),
-    # the upsampling halo-tile forward over several tiles, ragged
-    (32, 16, 1, 2, 2, 5, 9, 20),
+    # the upsampling halo-tile forwards over several tiles, ragged
+    (32, 16, 1, 2, 2, 5, 9, 20), (64, 32, 1, 2, 1, 4, 9, 17),
 ]
 
 
