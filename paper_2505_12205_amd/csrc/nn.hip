@@ -973,8 +973,9 @@ void launch_halo(int n, int d, int h, int w, int c, const uint16_t* x, const uin
 // U = 2), once.  Wave w owns the nine taps with kz = w: per 32-voxel K step
 // it reads the dz operand once and, for each ky, one halo row segment
 // (two aligned 16-byte reads) from which the three kx shifts are cut with
-// byte alignment -- dW[o][tap][c] += dz[p][o] X[p + tap - 1][c].  The
-// per-block sums go to the same partial layout as the direct kernels.
+// byte alignment -- dW[o][tap][c] += dz[p][o] X[p + tap - 1][c].  Layers of
+// 64 channels are split into 32-channel slices of co and ci (blockIdx.y).
+// The per-block sums go to the same partial layout as the direct kernels.
 template <int CO, int CI>
 struct WHalo {
   static constexpr int NO = CO / 16, NC = CI / 16;
@@ -1002,7 +1003,7 @@ __device__ __forceinline__ v8bf as_bf8(uint32_t a, uint32_t b, uint32_t c, uint3
 
 template <int CO, int CI, int U>
 __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restrict__ x,
-                                                         const uint16_t* __restrict__ dz, WGeo g,
+                                                         const uint16_t* __restrict__ dz, WGeo g, int cot, int cit,
                                                          float* __restrict__ part, float* __restrict__ dbpart) {
   using T = WHalo<CO, CI>;
   constexpr int NO = T::NO, NC = T::NC, TZ = T::TZ, TY = T::TY, R = T::R;
@@ -1011,6 +1012,8 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
   __shared__ __attribute__((aligned(16))) uint16_t xT[T::X_ELEMS];
   const int lane = threadIdx.x & 63, kz = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
+  const int nci = cit / CI;                                  // channel slices of this block
+  const int ci0 = (blockIdx.y % nci) * CI, co0 = (blockIdx.y / nci) * CO;
   v4f acc[9][NO * NC], accb[NO];
 #pragma unroll
   for (int t = 0; t < 9; ++t)
@@ -1036,7 +1039,7 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
       const int gz = z0 + (v >> 4) / TY, gy = y0 + (v >> 4) % TY, gx = x0 + (v & 15);
       uint4 val = {0u, 0u, 0u, 0u};
       if (gz < g.od && gy < g.oh && gx < g.ow)
-        val = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * CO + c8);
+        val = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * cot + co0 + c8);
       const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
       for (int j = 0; j < 8; ++j) dzT[(c8 + j) * DZS + v] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
@@ -1047,7 +1050,7 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
       const int qx = x0 - 1 + hx, qy = y0 - 1 + hy, qz = z0 - 1 + hz;
       uint4 val = {0u, 0u, 0u, 0u};
       if (qx >= 0 && qx < g.ow && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od)
-        val = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * CI + c8);
+        val = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * cit + ci0 + c8);
       const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
       for (int j = 0; j < 8; ++j)
@@ -1094,20 +1097,21 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
       for (int ct = 0; ct < NC; ++ct)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          part[(((long long)blockIdx.x * 27 + tap) * CO + ot * 16 + 4 * quad + r) * CI + ct * 16 + col] =
-              acc[t][ot * NC + ct][r];
+          part[(((long long)blockIdx.x * 27 + tap) * cot + co0 + ot * 16 + 4 * quad + r) * cit + ci0 + ct * 16 +
+               col] = acc[t][ot * NC + ct][r];
   }
-  if (kz == 0 && col == 0)
+  if (kz == 0 && col == 0 && ci0 == 0)
 #pragma unroll
     for (int ot = 0; ot < NO; ++ot)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dbpart[(long long)blockIdx.x * CO + ot * 16 + 4 * quad + r] = accb[ot][r];
+      for (int r = 0; r < 4; ++r) dbpart[(long long)blockIdx.x * cot + co0 + ot * 16 + 4 * quad + r] = accb[ot][r];
 }
 
 // voxel chunking of the weight gradient: about 2048 blocks (the per-tap
 // kernel has 27 blocks per chunk, the all-taps kernel one)
-// the halo-brick weight gradient takes stride-1 layers of up to 32 channels
-bool whalo_ok(const Geo& g, int stride) { return stride == 1 && g.co <= 32 && g.ci <= 32; }
+// the halo-brick weight gradient takes every stride-1 layer (64-channel
+// layers in 32-channel slices)
+bool whalo_ok(const Geo&, int stride) { return stride == 1; }
 
 template <int CO, int CI>
 WGeo whalo_geo(const Geo& g) {
@@ -1127,6 +1131,7 @@ WGeo whalo_geo(const Geo& g) {
   return w;
 }
 
+// the slice shape of a layer: min(channels, 32) for co and ci
 WGeo whalo_geo_of(const Geo& g) {
   if (g.ci == 16) return g.co == 16 ? whalo_geo<16, 16>(g) : whalo_geo<32, 16>(g);
   return g.co == 16 ? whalo_geo<16, 32>(g) : whalo_geo<32, 32>(g);
@@ -1136,10 +1141,11 @@ template <int CO, int CI>
 void launch_whalo_c(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, int nchunk, float* part,
                     float* dbpart, hipStream_t st) {
   const WGeo w = whalo_geo<CO, CI>(g);
+  const dim3 grid(nchunk, (g.co / CO) * (g.ci / CI));
   if (up == 1)
-    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 1>), dim3(nchunk), dim3(192), 0, st, x, dz, w, part, dbpart);
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 1>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part, dbpart);
   else
-    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 2>), dim3(nchunk), dim3(192), 0, st, x, dz, w, part, dbpart);
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 2>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part, dbpart);
 }
 
 void launch_whalo(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, int nchunk, float* part,
