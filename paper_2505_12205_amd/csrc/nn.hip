@@ -368,6 +368,98 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
 }
 
 // ---------------------------------------------------------------------------
+// data gradient of a stride-2 layer by parity class
+// ---------------------------------------------------------------------------
+// Input voxel q is read by output voxel p = (q + 1 - k) / 2 only through the
+// taps with q + 1 - k even: k = 1 where q is even and k in {0, 2} where q is
+// odd, per axis.  A wave takes 16 voxels of one x parity in a row
+// (x = 2 (i0 + l) + px) and MS rows of one y parity (y = y0 + 2 m) at one z,
+// so its tap set (1 to 8 of the 27 taps) is uniform and K = taps x co.
+struct S2Geo {
+  int n, d, h, w;      // layer input extent
+  int od, oh, ow, co;  // layer output extent, output channels
+  int nxt, nyg;        // 16-voxel tiles per x parity, y groups (both parities)
+  long long nwaves;
+};
+
+template <int CI>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t* __restrict__ dz,
+                                                          const uint16_t* __restrict__ wf, S2Geo g,
+                                                          const uint16_t* __restrict__ add,
+                                                          const uint16_t* __restrict__ mask,
+                                                          uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
+  constexpr int NS = CI / 16, MS = 8 / NS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  long long t = (long long)blockIdx.x * 4 + wv;
+  if (t >= g.nwaves) return;  // per wave: the kernel has no barrier
+  const int ixt = (int)(t % g.nxt);
+  t /= g.nxt;
+  const int px = (int)(t % 2);
+  t /= 2;
+  const int yg = (int)(t % g.nyg);
+  t /= g.nyg;
+  const int qz = (int)(t % g.d);
+  const int n = (int)(t / g.d);
+  const int py = yg & 1, y0 = (yg >> 1) * (2 * MS) + py, i0 = ixt * 16;
+  const int pz_odd = qz & 1;
+  const int nxk = px ? 2 : 1, nyk = py ? 2 : 1, nzk = pz_odd ? 2 : 1;
+  const int K = nxk * nyk * nzk * g.co, osh = ilog2(g.co);
+  const int qx = 2 * (i0 + col) + px;  // this lane's A row
+  v4f acc[MS][NS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const v8bf zero = {};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + 8 * quad;
+    const bool kin = k < K;
+    const int ti = kin ? (k >> osh) : 0, o = k - (ti << osh);
+    const int tx = ti % nxk, ty = (ti / nxk) % nyk, tz = ti / (nxk * nyk);
+    const int kx = px ? 2 * tx : 1, ky = py ? 2 * ty : 1, kz = pz_odd ? 2 * tz : 1;
+    const int tap = (kz * 3 + ky) * 3 + kx;
+    const int pz = (qz + 1 - kz) >> 1, ppx = (qx + 1 - kx) >> 1;
+    const bool okx = kin && qx < g.w && ppx >= 0 && ppx < g.ow && pz >= 0 && pz < g.od;
+    v8bf a[MS], b[NS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      const int qy = y0 + 2 * m, ppy = (qy + 1 - ky) >> 1;
+      const bool v = okx && qy < g.h && ppy >= 0 && ppy < g.oh;
+      a[m] = v ? ld8(dz + ((((long long)n * g.od + pz) * g.oh + ppy) * g.ow + ppx) * g.co + o) : zero;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      b[s] = kin ? ld8(wf + ((long long)(s * 16 + col) * 27 + (26 - tap)) * g.co + o) : zero;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+  }
+  // lane holds D[4 quad + r][col]: voxel i0 + 4 quad + r of row m, channel s*16 + col
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    const int qy = y0 + 2 * m;
+    if (qy >= g.h) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int qxx = 2 * (i0 + 4 * quad + r) + px;
+      if (qxx >= g.w) continue;
+      const long long v = (((long long)n * g.d + qz) * g.h + qy) * g.w + qxx;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const long long i = v * CI + s * 16 + col;
+        float val = acc[m][s][r];
+        if (add) val += bf2f(add[i]);
+        if (da) da[i] = f2bf(val);
+        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
+        dzp[i] = f2bf(val);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight gradient: block (chunk, tap) sums dz[v, o] X[src(v, tap), c] over
 // its voxel chunk; partial[chunk][tap][o][c]; db partials from tap 0 blocks
 // ---------------------------------------------------------------------------
@@ -899,6 +991,26 @@ void launch_bwd_data_su(const Geo& g, const uint16_t* dz, const uint16_t* wt, co
   else launch_bwd_data<64, S, U>(g, dz, wt, add, mask, da, dzp, st);
 }
 
+template <int CI>
+void launch_bwd_data_s2(const Geo& g, const uint16_t* dz, const uint16_t* wf, const uint16_t* add,
+                        const uint16_t* mask, uint16_t* da, uint16_t* dzp, hipStream_t st) {
+  constexpr int MS = 8 / (CI / 16);
+  S2Geo s2;
+  s2.n = g.n;
+  s2.d = g.d;
+  s2.h = g.h;
+  s2.w = g.w;
+  s2.od = g.od;
+  s2.oh = g.oh;
+  s2.ow = g.ow;
+  s2.co = g.co;
+  s2.nxt = ((g.w + 1) / 2 + 15) / 16;
+  s2.nyg = 2 * (((g.h + 1) / 2 + MS - 1) / MS);
+  s2.nwaves = (long long)s2.nxt * 2 * s2.nyg * g.d * g.n;
+  hipLaunchKernelGGL((k_conv_bwd_data_s2<CI>), dim3(blocks_for(s2.nwaves, 4)), dim3(256), 0, st, dz, wf, s2, add,
+                     mask, da, dzp);
+}
+
 template <int CO, int CI, int S, int U>
 void launch_bwd_w_one(const Geo& g, const uint16_t* x, const uint16_t* dz, int nchunk, long long vchunk,
                       float* part, float* dbpart, hipStream_t st) {
@@ -1160,9 +1272,11 @@ void launch_whalo(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, i
 }
 
 void wchunks(const Geo& g, int stride, int& nchunk, long long& vchunk) {
-  if (whalo_ok(g, stride)) {  // one chunk per block of the brick walk
+  if (whalo_ok(g, stride)) {  // one chunk per block of the brick walk, ~1024 blocks over the slices
     const long long nb = whalo_geo_of(g).nbricks;
-    nchunk = (int)(nb < kWHaloBlocks ? nb : kWHaloBlocks);
+    const int slices = (g.co / std::min(g.co, 32)) * (g.ci / std::min(g.ci, 32));
+    const int cap = kWHaloBlocks / slices;
+    nchunk = (int)(nb < cap ? nb : cap);
     if (nchunk < 1) nchunk = 1;
     vchunk = 0;
     return;
@@ -1227,7 +1341,9 @@ int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, c
     return check_launch("sg_conv3d_bwd_data");
   }
   if (stride == 1 && up == 1) launch_bwd_data_su<1, 1>(g, dz, wgt_f, add, mask, da, dzp, st);
-  else if (stride == 2) launch_bwd_data_su<2, 1>(g, dz, wgt_f, add, mask, da, dzp, st);
+  else if (stride == 2 && g.ci == 16) launch_bwd_data_s2<16>(g, dz, wgt_f, add, mask, da, dzp, st);
+  else if (stride == 2 && g.ci == 32) launch_bwd_data_s2<32>(g, dz, wgt_f, add, mask, da, dzp, st);
+  else if (stride == 2) launch_bwd_data_s2<64>(g, dz, wgt_f, add, mask, da, dzp, st);
   else launch_bwd_data_su<1, 2>(g, dz, wgt_f, add, mask, da, dzp, st);
   return check_launch("sg_conv3d_bwd_data");
 }

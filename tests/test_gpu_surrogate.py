@@ -82,6 +82,8 @@ CASES = [  # (ci, co, stride, up, n, d, h, w)
     (32, 16, 1, 1, 2, 7, 12, 20), (16, 32, 1, 2, 1, 4, 3, 9),
     # the upsampling halo-tile forwards over several tiles, ragged
     (32, 16, 1, 2, 2, 5, 9, 20), (64, 32, 1, 2, 1, 4, 9, 17),
+    # the stride-2 data gradient by parity class over several waves, ragged
+    (16, 32, 2, 1, 1, 9, 20, 37), (64, 32, 2, 1, 1, 5, 17, 33),
 ]
 
 
