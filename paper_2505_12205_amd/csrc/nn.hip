@@ -1094,6 +1094,7 @@ struct WHalo {
   static constexpr int TZ = CI == 16 ? 4 : 2, TY = (CI == 32 && CO == 32) ? 4 : 8;
   static constexpr int R = TZ * TY;                 // rows of 16 voxels
   static constexpr int HX = 18, HXP = 24, HY = TY + 2, HZ = TZ + 2;
+  static_assert(HXP >= 20, "halo rows are staged 20 wide");
   static constexpr int DZS = R * 16 + 8;            // dzT channel stride (elements), 4 banks apart
   static constexpr int XB = HZ * HY * HXP;          // halo elements per channel
   static constexpr int XCS = XB + 2 * ((20 - (XB / 2) % 64 + 64) % 64);  // 20 banks apart
@@ -1146,27 +1147,52 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
     const int n = r0 / g.ntz;
     const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
     __syncthreads();  // the previous brick's reads are done
-    for (int i = threadIdx.x; i < R * 16 * (CO / 8); i += 192) {
-      const int c8 = (i % (CO / 8)) * 8, v = i / (CO / 8);
-      const int gz = z0 + (v >> 4) / TY, gy = y0 + (v >> 4) % TY, gx = x0 + (v & 15);
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (gz < g.od && gy < g.oh && gx < g.ow)
-        val = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * cot + co0 + c8);
-      const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+    // transposed staging, four consecutive x voxels of one channel per
+    // 8-byte LDS write (the halo rows are staged 20 wide, inside HXP)
+    for (int i = threadIdx.x; i < R * 4 * (CO / 8); i += 192) {
+      const int c8 = (i % (CO / 8)) * 8, v4 = (i / (CO / 8)) * 4;
+      const int gz = z0 + (v4 >> 4) / TY, gy = y0 + (v4 >> 4) % TY;
+      uint4 val[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dzT[(c8 + j) * DZS + v] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
+      for (int e = 0; e < 4; ++e) {
+        const int gx = x0 + (v4 & 15) + e;
+        val[e] = (uint4){0u, 0u, 0u, 0u};
+        if (gz < g.od && gy < g.oh && gx < g.ow)
+          val[e] = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * cot + co0 + c8);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        uint32_t h[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t w = (j >> 1) == 0 ? val[e].x : (j >> 1) == 1 ? val[e].y : (j >> 1) == 2 ? val[e].z : val[e].w;
+          h[e] = (w >> (16 * (j & 1))) & 0xFFFFu;
+        }
+        *(uint2*)&dzT[(c8 + j) * DZS + v4] = (uint2){h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+      }
     }
-    for (int i = threadIdx.x; i < HZ * HY * HX * (CI / 8); i += 192) {
+    for (int i = threadIdx.x; i < HZ * HY * 5 * (CI / 8); i += 192) {
       const int c8 = (i % (CI / 8)) * 8, hv = i / (CI / 8);
-      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-      const int qx = x0 - 1 + hx, qy = y0 - 1 + hy, qz = z0 - 1 + hz;
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (qx >= 0 && qx < g.ow && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od)
-        val = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * cit + ci0 + c8);
-      const uint32_t w4[4] = {val.x, val.y, val.z, val.w};
+      const int hx4 = (hv % 5) * 4, hy = (hv / 5) % HY, hz = hv / (5 * HY);
+      const int qy = y0 - 1 + hy, qz = z0 - 1 + hz;
+      uint4 val[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        xT[(c8 + j) * XCS + (hz * HY + hy) * HXP + hx] = (uint16_t)(w4[j >> 1] >> (16 * (j & 1)));
+      for (int e = 0; e < 4; ++e) {
+        const int qx = x0 - 1 + hx4 + e;
+        val[e] = (uint4){0u, 0u, 0u, 0u};
+        if (qx >= 0 && qx < g.ow && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od)
+          val[e] = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * cit + ci0 + c8);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        uint32_t h[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t w = (j >> 1) == 0 ? val[e].x : (j >> 1) == 1 ? val[e].y : (j >> 1) == 2 ? val[e].z : val[e].w;
+          h[e] = (w >> (16 * (j & 1))) & 0xFFFFu;
+        }
+        *(uint2*)&xT[(c8 + j) * XCS + (hz * HY + hy) * HXP + hx4] = (uint2){h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+      }
     }
     __syncthreads();
     for (int st = 0; st < R / 2; ++st) {
