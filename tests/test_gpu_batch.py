@@ -48,6 +48,24 @@ def test_batch_equals_standalone_bitwise(storage):
         assert (hb == hs).all() and (gb == gs).all() and (ub == us).all(), d
 
 
+def test_bgk_batch_equals_standalone_bitwise():
+    """The operator flag reaches the batched launches: a batch of BGK domains
+    (x-wall lanes, faces, inlet and outlet) equals each domain run alone with
+    BGK, and differs from WMRT."""
+    lbm = _lbm()
+    doms = [(dict(c, collision="bgk"), p, u) for c, p, u in _small_sweep(seed=3)[:2]]
+    _log(f"[gpu] BGK batch of {len(doms)}")
+    b = lbm.Batch(doms, storage="fp32").step(41)
+    for d, (cfg, phi0, u0) in enumerate(doms):
+        s = lbm.Sim(cfg, phi0, u0).step(41)
+        hb, gb, ub = b.export_state(d)
+        hs, gs, us = s.export_state()
+        assert (hb == hs).all() and (gb == gs).all() and (ub == us).all(), d
+    cfg, phi0, u0 = doms[0]
+    w = lbm.Sim(dict(cfg, collision="wmrt"), phi0, u0).step(41)
+    assert not (w.export_state()[1] == b.export_state(0)[1]).all()
+
+
 def test_batch_domain_matches_oracle():
     lbm = _lbm()
     doms = _small_sweep(seed=7)
