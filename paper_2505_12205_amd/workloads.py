@@ -94,25 +94,6 @@ def laplace3d(n=100, radius=20.0, sigma=0.005, rho_ratio=1000.0, tau=0.5, xi=4.0
     return cfg, _tanh_profile(radius - r, xi), None
 
 
-def laplace_pressure_jump(phi, p, xi=4.0):
-    """(Delta p, R) of a centred static drop: the mean pressure inside
-    r < R - 2 xi minus the mean outside r > R + 2 xi, with the radius of the
-    sphere of the drop's volume, R = (3 sum(phi) / (4 pi))^(1/3) (3D) or
-    (sum(phi) / pi)^(1/2) (2D)."""
-    phi = np.asarray(phi, dtype=np.float64)
-    p = np.asarray(p, dtype=np.float64)
-    nz, ny, nx = phi.shape
-    if nz > 1:
-        R = (3.0 * phi.sum() / (4.0 * np.pi)) ** (1.0 / 3.0)
-        x, y, z = _grid(nx, ny, nz)
-        r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2 + (z - nz / 2.0) ** 2)
-    else:
-        R = np.sqrt(phi.sum() / np.pi)
-        x, y, _ = _grid(nx, ny, 1)
-        r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2)
-    return p[r < R - 2 * xi].mean() - p[r > R + 2 * xi].mean(), R
-
-
 def rt_params(lref=256, atwood=0.5, reynolds=3000.0, u0=0.04, visc_ratio=1.0,
               peclet=1000.0, capillary=0.26, xi=5.0):
     """Lattice-unit parameters of the Rayleigh-Taylor case.
