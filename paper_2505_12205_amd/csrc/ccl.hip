@@ -12,8 +12,9 @@
 //             is joined once, at the start of its overlap;
 //   k_flatten every liquid node takes its root.
 // Statistics: the roots are compacted in ascending order (counts per chunk
-// of 4096 nodes, one scan, ordered writes), then every run of equal labels within a wave
-// adds its length and extent with one set of atomics.
+// of 4096 nodes, one scan, ordered writes), then every run of equal labels
+// within a wave adds its length and extent to a per-block table in LDS,
+// flushed once per block.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -210,33 +211,71 @@ __global__ __launch_bounds__(TPB) void k_root_write(const int* __restrict__ L, E
   }
 }
 
-// size and extent: one set of atomics per run of equal labels within a wave row
+// size and extent: every run of equal labels within a wave row adds its
+// length and extent to its component's entry in a per-block LDS table (open
+// addressing on the component index), which is added to the outputs once per
+// block; a run whose probe finds no slot goes to the outputs directly
+constexpr int ATAB = 128, APROBE = 8;
+
 __global__ __launch_bounds__(TPB) void k_accumulate(const int* __restrict__ L, Ext e, int axis,
                                                     const int* __restrict__ cid, int cap, int* size, int* lo,
                                                     int* hi) {
-  const int i = blockIdx.x * TPB + threadIdx.x;
+  __shared__ int tk[ATAB], ts[ATAB], tlo[ATAB], thi[ATAB];
+  for (int t = threadIdx.x; t < ATAB; t += TPB) {
+    tk[t] = -1;
+    ts[t] = 0;
+    tlo[t] = INT_MAX;
+    thi[t] = -1;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const bool valid = i < e.N;
-  const int l = valid ? L[i] : -1;
-  const int lp = __shfl_up(l, 1);
-  const int x = valid ? i % e.nx : 0;
-  const bool fg = l >= 0;
-  const bool start = fg && (lane == 0 || lp != l || x == 0);
-  const uint64_t ms = __ballot(start);
-  const uint64_t brk = ms | ~__ballot(fg);  // lanes that do not continue the lane before
-  if (!start) return;
-  const uint64_t after = brk & ~lanes_upto(lane);
-  const int end = after ? __ffsll((long long)after) - 2 : 63;  // last lane of this run
-  const int len = end - lane + 1;
-  const int k = cid[l];
-  if (k >= cap) return;
-  int c;
-  if (axis == 0) c = x;
-  else if (axis == 1) c = (i / e.nx) % e.ny;
-  else c = i / (e.nx * e.ny);
-  atomicAdd(size + k, len);
-  atomicMin(lo + k, c);
-  atomicMax(hi + k, axis == 0 ? c + len - 1 : c);
+  for (int sl = 0; sl < SLABS; ++sl) {
+    const int i = blockIdx.x * CHUNK + sl * TPB + threadIdx.x;
+    const bool valid = i < e.N;
+    const int l = valid ? L[i] : -1;
+    const int lp = __shfl_up(l, 1);
+    const int x = valid ? i % e.nx : 0;
+    const bool fg = l >= 0;
+    const bool start = fg && (lane == 0 || lp != l || x == 0);
+    const uint64_t ms = __ballot(start);
+    const uint64_t brk = ms | ~__ballot(fg);  // lanes that do not continue the lane before
+    if (!start) continue;
+    const uint64_t after = brk & ~lanes_upto(lane);
+    const int end = after ? __ffsll((long long)after) - 2 : 63;  // last lane of this run
+    const int len = end - lane + 1;
+    const int k = cid[l];
+    if (k >= cap) continue;
+    int c;
+    if (axis == 0) c = x;
+    else if (axis == 1) c = (i / e.nx) % e.ny;
+    else c = i / (e.nx * e.ny);
+    const int chi = axis == 0 ? c + len - 1 : c;
+    int slot = -1;
+    for (int p = 0, h = k & (ATAB - 1); p < APROBE; ++p, h = (h + 1) & (ATAB - 1)) {
+      const int old = atomicCAS(&tk[h], -1, k);
+      if (old == -1 || old == k) {
+        slot = h;
+        break;
+      }
+    }
+    if (slot >= 0) {
+      atomicAdd(&ts[slot], len);
+      atomicMin(&tlo[slot], c);
+      atomicMax(&thi[slot], chi);
+    } else {
+      atomicAdd(size + k, len);
+      atomicMin(lo + k, c);
+      atomicMax(hi + k, chi);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ATAB; t += TPB) {
+    const int k = tk[t];
+    if (k < 0) continue;
+    atomicAdd(size + k, ts[t]);
+    atomicMin(lo + k, tlo[t]);
+    atomicMax(hi + k, thi[t]);
+  }
 }
 
 __global__ void k_deq(const int* __restrict__ ncomp, int cap, bool three_d, const int* __restrict__ size,
@@ -323,7 +362,7 @@ int dr_components(const int* label, int nx, int ny, int nz, int axis, int cap, i
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, w.nchunk, off, nc);
   hipLaunchKernelGGL(k_root_write, dim3(w.nchunk), dim3(TPB), 0, st, label, e, off, cap, cid, root, size, lo,
                      hi);
-  hipLaunchKernelGGL(k_accumulate, dim3(w.nblk), dim3(TPB), 0, st, label, e, axis, cid, cap, size, lo, hi);
+  hipLaunchKernelGGL(k_accumulate, dim3(w.nchunk), dim3(TPB), 0, st, label, e, axis, cid, cap, size, lo, hi);
   if (cap > 0)
     hipLaunchKernelGGL(k_deq, dim3((cap + 255) / 256), dim3(256), 0, st, nc, cap, nz > 1, size, deq);
   HIPCHK(hipGetLastError());
