@@ -60,10 +60,15 @@ struct KBufs {
 template <int ST>
 struct Codec;
 
+// The interior kernels address the populations, phase field and velocity
+// through global-address-space pointers: the buffers come from a device-side
+// domain table, and without the qualifier every access would be a generic
+// (flat) one.  The codecs take either pointer kind.
+
 // store with an optional non-temporal hint (the written populations are not
 // read again within the step, so they need not stay in L2)
-template <bool NT, typename T, typename I>
-__device__ __forceinline__ void put(T* p, I i, T v) {
+template <bool NT, typename P, typename I, typename T>
+__device__ __forceinline__ void put(P p, I i, T v) {
   if (NT)
     __builtin_nontemporal_store(v, p + i);
   else
@@ -73,31 +78,31 @@ __device__ __forceinline__ void put(T* p, I i, T v) {
 template <>
 struct Codec<0> {  // FP32 as is
   using T = float;
-  template <typename I>
-  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) { return p[i]; }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) { put<NT>(p, i, v); }
-  template <typename I>
-  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return p[i]; }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, v); }
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_h(P p, I i, float w, float ref) { return p[i]; }
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_h(P p, I i, float v, float iw, float ref) { put<NT>(p, i, (T)v); }
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_g(P p, I i, float w) { return p[i]; }
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_g(P p, I i, float v, float iw) { put<NT>(p, i, (T)v); }
 };
 
 template <>
 struct Codec<1> {  // FP16 deviations: h -> h/w - phi_ref, g -> g/w
   using T = _Float16;
-  template <typename I>
-  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) {
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_h(P p, I i, float w, float ref) {
     return w * ((float)p[i] + ref);
   }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) {
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_h(P p, I i, float v, float iw, float ref) {
     put<NT>(p, i, (T)(v * iw - ref));
   }
-  template <typename I>
-  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return w * (float)p[i]; }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, (T)(v * iw)); }
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_g(P p, I i, float w) { return w * (float)p[i]; }
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_g(P p, I i, float v, float iw) { put<NT>(p, i, (T)(v * iw)); }
 };
 
 __device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
@@ -110,18 +115,18 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uin
 template <>
 struct Codec<2> {  // BF16 deviations, same encoding as FP16
   using T = uint16_t;
-  template <typename I>
-  static __device__ __forceinline__ float ld_h(const T* p, I i, float w, float ref) {
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_h(P p, I i, float w, float ref) {
     return w * (bf2f(p[i]) + ref);
   }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_h(T* p, I i, float v, float iw, float ref) {
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_h(P p, I i, float v, float iw, float ref) {
     put<NT>(p, i, f2bf(v * iw - ref));
   }
-  template <typename I>
-  static __device__ __forceinline__ float ld_g(const T* p, I i, float w) { return w * bf2f(p[i]); }
-  template <bool NT = false, typename I = size_t>
-  static __device__ __forceinline__ void st_g(T* p, I i, float v, float iw) { put<NT>(p, i, f2bf(v * iw)); }
+  template <typename P, typename I>
+  static __device__ __forceinline__ float ld_g(P p, I i, float w) { return w * bf2f(p[i]); }
+  template <bool NT = false, typename P = void, typename I = size_t>
+  static __device__ __forceinline__ void st_g(P p, I i, float v, float iw) { put<NT>(p, i, f2bf(v * iw)); }
 };
 
 // ---------------------------------------------------------------------------
@@ -759,13 +764,17 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   const int on = WALL ? wall_lane(P, c) : 0;
   const int onns = on & P.nsbits;
   const unsigned N = (unsigned)P.N;
-  Ty* Gp = (Ty*)B.g;  // loads and stores go through one pointer: in place
-  Ty* Hp = (Ty*)B.h;
+  using GTy = __attribute__((address_space(1))) Ty;
+  using GF = __attribute__((address_space(1))) float;
+  GTy* Gp = (GTy*)B.g;  // loads and stores go through one pointer: in place
+  GTy* Hp = (GTy*)B.h;
+  const GF* Phi = (const GF*)B.phi;
+  GF* Uv = (GF*)B.u;
 
-  const float phi = B.phi[node];
+  const float phi = Phi[node];
   float gr[3] = {0.f, 0.f, 0.f}, lap = 0.f;
 #pragma unroll
-  for (int a = 1; a < Q; ++a) stencil_add<Q>(a, B.phi[nb.at<Q>(a)], phi, gr, lap);
+  for (int a = 1; a < Q; ++a) stencil_add<Q>(a, Phi[nb.at<Q>(a)], phi, gr, lap);
   gr[0] *= 3.0f;
   gr[1] *= 3.0f;
   gr[2] *= 3.0f;
@@ -799,8 +808,8 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     if (b < a) continue;
     int ia, ib;
     int ra, rb;
-    const Ty* Ga = Gp + sbase(b, ia, ra);
-    const Ty* Gb = Gp + sbase(a, ib, rb);
+    const GTy* Ga = Gp + sbase(b, ia, ra);
+    const GTy* Gb = Gp + sbase(a, ib, rb);
     const float ga = C::ld_g(Ga, ia, L::w[a]);
     const float gb = C::ld_g(Gb, ib, L::w[b]);
     if (BGK) {
@@ -817,21 +826,21 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     if (D == 3 && L::ex[a] && L::ez[a]) S.xz += (L::ex[a] * L::ez[a]) * s;
   }
   float up[3];
-  up[0] = B.u[node];
-  up[1] = B.u[N + node];
-  up[2] = (D == 3) ? B.u[2 * N + node] : 0.0f;
+  up[0] = Uv[node];
+  up[1] = Uv[N + node];
+  up[2] = (D == 3) ? Uv[2 * N + node] : 0.0f;
   NodeCtx X;
   macro<Q, BGK>(P, phi, gr, lap, p, j, S, up, X);
-  B.u[node] = X.u[0];
-  B.u[N + node] = X.u[1];
-  if (D == 3) B.u[2 * N + node] = X.u[2];
+  Uv[node] = X.u[0];
+  Uv[N + node] = X.u[1];
+  if (D == 3) Uv[2 * N + node] = X.u[2];
 
   // per-node constants of the pair updates
   const float gA = X.p - 1.5f * X.uu;  // f^eq: w (gA + 4.5 eu^2 + 3 eu)
   const float hB = 1.0f - 1.5f * X.uu; // h^eq: phi w (hB + 4.5 eu^2 + 3 eu)
   const float hf = 0.5f * X.f3r;       // half of F_a / (w e.F)
   const float om = X.om;
-  const float ref = (ST == 0) ? 0.0f : B.ref[node];
+  const float ref = (ST == 0) ? 0.0f : ((const GF*)B.ref)[node];
 
   // rest population
   const float h0 = C::ld_h(Hp, (unsigned)node, L::w[0], ref);
@@ -856,10 +865,10 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     int rdr_b, rdr_a;  // readers of the slots of a's and b's post-collision values
     const size_t oa = sbase(b, ia, rdr_b);  // a is read here, b's post value goes here
     const size_t ob = sbase(a, ib, rdr_a);
-    Ty* Ha = Hp + oa;
-    Ty* Hb = Hp + ob;
-    Ty* Ga = Gp + oa;
-    Ty* Gb = Gp + ob;
+    GTy* Ha = Hp + oa;
+    GTy* Hb = Hp + ob;
+    GTy* Ga = Gp + oa;
+    GTy* Gb = Gp + ob;
     const float ha = C::ld_h(Ha, ia, w, ref);
     const float hb = C::ld_h(Hb, ib, w, ref);
     const float eu = ex * X.u[0] + ey * X.u[1] + ez * X.u[2];
@@ -894,8 +903,8 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const float da = om * (hsym + hanti - ha) + fphi;
     const float db = om * (hsym - hanti - hb) - fphi;
     dsum += da + db;
-    const float wra = (ST == 0) ? 0.0f : B.phi[rdr_a];  // readers' phase field
-    const float wrb = (ST == 0) ? 0.0f : B.phi[rdr_b];
+    const float wra = (ST == 0) ? 0.0f : Phi[rdr_a];  // readers' phase field
+    const float wrb = (ST == 0) ? 0.0f : Phi[rdr_b];
     C::template st_h<NT>(Hb, ib, ha + da, 1.0f / w, wra);
     C::template st_h<NT>(Ha, ia, hb + db, 1.0f / w, wrb);
   }
@@ -1042,8 +1051,10 @@ __device__ __forceinline__ void phi_fast(const KParams& P, const KBufs& B, const
   const int on = WALL ? wall_lane(P, c) : 0;
   const int onns = on & P.nsbits;
   const size_t NN = (size_t)P.N;
-  const Ty* Hp = (const Ty*)B.h;
-  const float ref = (ST == 0) ? 0.0f : B.ref[node];
+  using GTy = __attribute__((address_space(1))) Ty;
+  using GF = __attribute__((address_space(1))) float;
+  const GTy* Hp = (const GTy*)B.h;
+  const float ref = (ST == 0) ? 0.0f : ((const GF*)B.ref)[node];
   float s = 0.0f, cc = 0.0f;
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -1054,7 +1065,7 @@ __device__ __forceinline__ void phi_fast(const KParams& P, const KBufs& B, const
     const int idx = WALL ? nd + (pop - pop0) * P.N : nd;
     kahan_add(C::ld_h(Hp + (size_t)pop0 * NN, idx, L::w[a], ref), s, cc);
   }
-  B.phi_out[node] = s - cc;
+  ((GF*)B.phi_out)[node] = s - cc;
 }
 
 template <int Q, int ST, int ODD>
