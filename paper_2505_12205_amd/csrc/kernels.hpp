@@ -773,8 +773,12 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
 
   const float phi = Phi[node];
   float gr[3] = {0.f, 0.f, 0.f}, lap = 0.f;
+  float phn[Q];  // neighbours' phase field, kept: the 16-bit forms encode with the readers' one
 #pragma unroll
-  for (int a = 1; a < Q; ++a) stencil_add<Q>(a, Phi[nb.at<Q>(a)], phi, gr, lap);
+  for (int a = 1; a < Q; ++a) {
+    phn[a] = Phi[nb.at<Q>(a)];
+    stencil_add<Q>(a, phn[a], phi, gr, lap);
+  }
   gr[0] *= 3.0f;
   gr[1] *= 3.0f;
   gr[2] *= 3.0f;
@@ -903,8 +907,11 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const float da = om * (hsym + hanti - ha) + fphi;
     const float db = om * (hsym - hanti - hb) - fphi;
     dsum += da + db;
-    const float wra = (ST == 0) ? 0.0f : Phi[rdr_a];  // readers' phase field
-    const float wrb = (ST == 0) ? 0.0f : Phi[rdr_b];
+    // readers' phase field: the stencil's neighbour in direction a (b), the
+    // clamped one at a free-slip x wall, or the node itself where a no-slip
+    // x wall sends the value back (slot_of)
+    const float wra = (ST == 0) ? 0.0f : ((WALL && wall_hit<Q>(onns, a)) ? phi : phn[a]);
+    const float wrb = (ST == 0) ? 0.0f : ((WALL && wall_hit<Q>(onns, b)) ? phi : phn[b]);
     C::template st_h<NT>(Hb, ib, ha + da, 1.0f / w, wra);
     C::template st_h<NT>(Ha, ia, hb + db, 1.0f / w, wrb);
   }
