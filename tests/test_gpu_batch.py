@@ -66,6 +66,30 @@ def test_bgk_batch_equals_standalone_bitwise():
     assert not (w.export_state()[1] == b.export_state(0)[1]).all()
 
 
+def test_diverged_domain_is_isolated_and_reported():
+    """A non-finite value in one domain stays in that domain: the other
+    domain still equals its standalone run bit for bit; reduce() raises
+    LBM_EUNSTABLE and reduce(strict=False) returns the per-domain values."""
+    lbm = _lbm()
+    doms = _small_sweep(seed=5)[:2]
+    cfg1, phi1, u1 = doms[1]
+    phi1 = phi1.copy()
+    phi1[phi1.shape[0] // 2, phi1.shape[1] // 2, phi1.shape[2] // 2] = np.nan
+    doms[1] = (cfg1, phi1, u1)
+    _log("[gpu] batch with a non-finite domain")
+    b = lbm.Batch(doms, storage="fp32").step(12)
+    with pytest.raises(lbm.LbmError) as ei:
+        b.reduce()
+    assert ei.value.code == lbm.LBM_EUNSTABLE
+    mass, ke = b.reduce(strict=False)
+    assert np.isfinite(mass[0]) and np.isfinite(ke[0]) and not np.isfinite(mass[1])
+    cfg0, phi0, u0 = doms[0]
+    s = lbm.Sim(cfg0, phi0, u0).step(12)
+    hb, gb, ub = b.export_state(0)
+    hs, gs, us = s.export_state()
+    assert (hb == hs).all() and (gb == gs).all() and (ub == us).all()
+
+
 def test_batch_domain_matches_oracle():
     lbm = _lbm()
     doms = _small_sweep(seed=7)
