@@ -128,6 +128,47 @@ def rt3d(nx=256, ny=1024, nz=256, lref=256, amp_frac=0.1, **kw):
     return cfg, phi0, None
 
 
+# the table of Rayleigh-Taylor cases: density ratio, viscosity ratio, Re,
+# Pe, Ca (None: no surface tension), interface width, dimension
+RT_CASES = {
+    "a": dict(rho_ratio=3.0, visc_ratio=1.0, reynolds=3000.0, peclet=1000.0, capillary=0.26, xi=4.0, dim=2),
+    "b": dict(rho_ratio=1000.0, visc_ratio=100.0, reynolds=3000.0, peclet=1000.0, capillary=0.44, xi=4.0, dim=2),
+    "c": dict(rho_ratio=3.0, visc_ratio=3.0, reynolds=128.0, peclet=744.0, capillary=None, xi=5.0, dim=3),
+    "d": dict(rho_ratio=1000.0, visc_ratio=100.0, reynolds=3000.0, peclet=200.0, capillary=8.7, xi=5.0, dim=3),
+}
+
+
+def rt_case(case, n=None, lref=256, amp_frac=0.1):
+    """One of the four Rayleigh-Taylor cases of the paper's table: an
+    L0 x 4 L0 (2D) or L0 x 4 L0 x L0 (3D) box, walls at the bottom and top,
+    periodic sides, heavy fluid above a cosine-perturbed interface.  The
+    parameters are those of L0 = lref; n (default lref) sets the lateral
+    extent, so that a small copy keeps the per-node arithmetic.  The
+    viscosity ratio is dynamic (mu_H / mu_L)."""
+    c = RT_CASES[case]
+    n = lref if n is None else n
+    at = (c["rho_ratio"] - 1.0) / (c["rho_ratio"] + 1.0)
+    p = rt_params(lref=lref, atwood=at, reynolds=c["reynolds"], visc_ratio=c["visc_ratio"], peclet=c["peclet"],
+                  capillary=c["capillary"] or 1.0, xi=c["xi"])
+    sigma = p["sigma"] if c["capillary"] else 0.0
+    if c["dim"] == 2:
+        nx, ny, nz = n, 4 * n, 1
+        bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
+        grav = (0.0, -p["g"], 0.0)
+    else:
+        nx, ny, nz = n, 4 * n, n
+        bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
+        grav = (0.0, -p["g"], 0.0)
+    cfg = dict(q=9 if c["dim"] == 2 else 19, nx=nx, ny=ny, nz=nz, rho_h=p["rho_h"], rho_l=p["rho_l"],
+               tau_h=p["tau_h"], tau_l=p["tau_l"], sigma=sigma, xi=p["xi"], mobility=p["mobility"],
+               gravity=grav, body_force="rho_minus_rhol", bc=bc, name=f"rt_case_{case}_{nx}x{ny}x{nz}")
+    x, y, z = _grid(nx, ny, nz)
+    y0 = ny / 2.0 + amp_frac * nx * np.cos(2 * np.pi * x / nx)
+    if c["dim"] == 3:
+        y0 = ny / 2.0 + 0.5 * amp_frac * nx * (np.cos(2 * np.pi * x / nx) + np.cos(2 * np.pi * z / nz))
+    return cfg, _tanh_profile(y - y0, p["xi"]), None
+
+
 # --------------------------------------------------------------------------
 # 3D liquid jet (D3Q19; free-slip sides, circular velocity inlet at z = 0,
 # convective outlet at z = nz - 1, gravity along +z)

@@ -134,3 +134,96 @@ def test_capillary_wave_density_ratio_1000():
     _log("LBM " + " ".join(f"{a:+.3f}" for a in amps[::4]))
     _log("ref " + " ".join(f"{a:+.3f}" for a in ref[::4]))
     assert err < 0.15
+
+
+@pytest.mark.parametrize("case,n", [("a", 32), ("b", 32), ("c", 16), ("d", 16)])
+def test_rt_case_one_step_every_node(case, n):
+    """The Rayleigh-Taylor cases of the paper's table (a, b in 2D, c, d in
+    3D; per-node parameters of L0 = 256) on small seeded copies: after 60
+    steps, one even and one odd step at every node from the same FP32 state
+    against the FP64 oracle, to FP32 rounding."""
+    lbm = _lbm()
+    cfg, phi0, u0 = W.rt_case(case, n=n)
+    phi0, u0 = W.perturb(phi0, u0, 3, 0.01, 1e-4)
+    s = lbm.Sim(cfg, phi0, u0).step(60)
+    q = cfg["q"]
+    for _ in range(2):
+        h, g, u = [t.cpu().numpy() for t in s.export_state()]
+        _log(f"[gpu] {cfg['name']} one step at parity {s.steps_done % 2}")
+        s.step(1)
+        h1, g1, u1 = [t.cpu().numpy() for t in s.export_state()]
+        ho, go, uo = oracle.step_nodes_f32(cfg, h, g, u, np.arange(h.reshape(q, -1).shape[1]))
+        eh = np.abs(h1.reshape(q, -1).T - ho).max()
+        eg = np.abs(g1.reshape(q, -1).T - go).max()
+        eu = np.abs(u1.reshape(3, -1).T - uo).max()
+        _log(f"rt case {case} one step: max|dh|={eh:.3e} max|dg|={eg:.3e} max|du|={eu:.3e}")
+        assert eh < 2e-7 and eg < 2e-7 and eu < 2e-7
+
+
+@pytest.mark.parametrize("case,n,steps", [("a", 32, 1000), ("b", 32, 1000), ("c", 16, 500), ("d", 16, 500)])
+def test_rt_case_copy_trajectory(case, n, steps):
+    """The same copies over several hundred steps against the FP64 oracle.
+    The one-step test above shows the step itself agrees to FP32 rounding;
+    over many steps these cases amplify that rounding where the heavy bulk
+    sits slightly off phi = 1 with a vanishing gradient: the interface normal
+    grad phi / |grad phi| is ill-conditioned there and a rounding-level change
+    turns the sharpening term, of size (1 - 4 (phi - 1/2)^2) / xi.  The FP32
+    trajectories stay within 1e-3 of the FP64 one (7e-4 measured)."""
+    lbm = _lbm()
+    cfg, phi0, u0 = W.rt_case(case, n=n)
+    phi0, u0 = W.perturb(phi0, u0, 3, 0.01, 1e-4)
+    o = oracle.Oracle(cfg).init(phi0, u0)
+    s = lbm.Sim(cfg, phi0, u0)
+    errs = []
+    for k in range(4):
+        o.step(steps // 4)
+        s.step(steps // 4)
+        phi_o = o.fields()[0]
+        phi_g = s.fields()[0].cpu().numpy().astype(np.float64)
+        errs.append(float(np.abs(phi_g - phi_o).max()))
+    _log(f"rt case {case}: max|dphi| at steps " + " ".join(f"{(k + 1) * steps // 4}:{e:.2e}" for k, e in enumerate(errs)))
+    assert max(errs) <= 1e-3
+
+
+def _front_positions(phi, lref):
+    """Bubble front (highest light-fluid point) and spike tip (lowest heavy
+    point) along y, in units of L0, relative to the box centre: the
+    levels where the column-wise extreme of phi crosses 1/2."""
+    ny = phi.shape[1]
+    heavy = phi > 0.5                           # [nz, ny, nx]
+    rows = heavy.any(axis=(0, 2))
+    light = (~heavy).any(axis=(0, 2))
+    spike = np.argmax(rows)                     # lowest y holding heavy fluid
+    bubble = ny - 1 - np.argmax(light[::-1])    # highest y holding light fluid
+    return (bubble - ny / 2) / lref, (spike - ny / 2) / lref
+
+
+@pytest.mark.parametrize("case", ["a", "b", "c", "d"])
+def test_rt_case_runs_and_conserves_mass(case):
+    """Each case at the paper's parameters (L0 = 256 in 2D; a 64-wide copy of
+    the same per-node parameters in 3D) to t* = t U0 / L0 = 2: it stays
+    finite, conserves sum phi in FP32 to 1e-6 per 1000 steps, and the heavy
+    fluid penetrates (the spike tip moves below its initial level).  The
+    bubble and spike histories are logged; the published curves they would
+    be compared with are external data."""
+    lbm = _lbm()
+    n = 256 if case in "ab" else 64
+    cfg, phi0, u0 = W.rt_case(case, n=n)
+    steps = 2 * 256 * 25  # t* = 2 with U0 = 0.04, L0 = 256 (6400 steps per unit)
+    _log(f"[gpu] {cfg['name']} {steps} steps")
+    s = lbm.Sim(cfg, phi0, u0)
+    m0, _ = s.reduce()
+    hist = []
+    for k in range(8):
+        s.step(steps // 8)
+        phi = s.fields()[0].cpu().numpy()
+        hist.append(_front_positions(phi, 256.0))
+    m1, ke = s.reduce()
+    drift = abs(m1 - m0) / m0
+    _log(f"rt case {case}: mass drift {drift:.2e} over {steps} steps, kinetic {ke:.3e}")
+    _log("t*      " + " ".join(f"{2 * (k + 1) / 8:.2f}" for k in range(8)))
+    _log("bubble  " + " ".join(f"{b:+.3f}" for b, _ in hist))
+    _log("spike   " + " ".join(f"{sp:+.3f}" for _, sp in hist))
+    assert np.isfinite(ke)
+    assert drift <= 1e-6 * steps / 1000
+    assert hist[-1][1] < hist[0][1] <= 0.0
