@@ -232,7 +232,7 @@ def main():
                     help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
 
