@@ -31,7 +31,13 @@ def run(steps=9600, start=4800, every=320, storage="fp16", n=64, log=print):
     dj = 2.0 * cfgs[0]["inlet_radius"]
     b = lbm.Batch(doms, storage=storage)
     t0 = time.perf_counter()
-    b.step(start)
+    done = 0
+    while done < start:
+        k = min(1600, start - done)
+        b.step(k)
+        done += k
+        torch.cuda.synchronize()
+        log(f"[jet_study] step {done}: advancing to the first sample, {time.perf_counter() - t0:.0f} s")
     alive = np.ones(n, bool)
     lb = [[] for _ in range(n)]
     de = [[] for _ in range(n)]
