@@ -73,6 +73,7 @@ def lib():
         L.ora_get_state.argtypes = [C.c_void_p, dp, dp, dp]
         L.ora_step.argtypes = [C.c_void_p, C.c_int]
         L.ora_fields.argtypes = [C.c_void_p, dp, dp, dp]
+        L.ora_step_h_prescribed.argtypes = [C.c_void_p, dp, dp, C.c_int]
         L.ora_reduce.argtypes = [C.c_void_p, dp, dp]
         L.ora_step_nodes_f32.argtypes = [C.POINTER(Params), fp, fp, fp, C.c_long, lp, dp, dp, dp]
         L.ora_feq.argtypes = [C.c_int, C.c_double, dp, dp]
@@ -176,6 +177,16 @@ class Oracle:
 
     def step(self, n: int = 1):
         lib().ora_step(self._h, int(n))
+        return self
+
+    def step_h_prescribed(self, u_field, scales):
+        """Advance only the phase-field set, len(scales) steps, under the
+        prescribed velocity scales[k] * u_field (u_field: [3, nz, ny, nx])."""
+        u, up = _d(np.asarray(u_field).reshape(-1))
+        assert u.size == 3 * self.N
+        sc, sp = _d(np.asarray(scales, float).reshape(-1))
+        if lib().ora_step_h_prescribed(self._h, up, sp, int(sc.size)) != 0:
+            raise ValueError("prescribed-velocity transport needs periodic or wall faces")
         return self
 
     def state(self):

@@ -955,6 +955,64 @@ int ora_step(ora_sim* s, int nsteps) {
   return 0;
 }
 
+/* Phase-field transport alone under a prescribed velocity (section
+ * "Circular Interface in a Shear Flow": the velocity is imposed and only the
+ * phase field evolves).  Each of the nsteps steps is
+ *   phi = sum h;  h+ = collision of Eq. lbe_interface with u = scale[k] u_field
+ *   (the gradient of phi and the forcing term as in the full step);
+ *   pull streaming of h with the wall and periodic rules of the full step.
+ * The hydrodynamic set and the stored velocity are left untouched.  Faces
+ * with a velocity inlet or a convective outlet are rejected (returns -1). */
+int ora_step_h_prescribed(ora_sim* s, const double* u_field, const double* scale, int nsteps) {
+  const lattice_t* L = s->L;
+  const long N = s->N;
+  const int q = L->q;
+  for (int f = 0; f < 6; ++f)
+    if (s->P.bc[f] == ORA_INLET || s->P.bc[f] == ORA_OUTLET) return -1;
+  for (int it = 0; it < nsteps; ++it) {
+    compute_phi(s);
+    const double sc = scale[it];
+#pragma omp parallel
+    {
+      ctx_t c;
+      ctx_full(s, &c);
+      c.phi = s->phi;
+#pragma omp for schedule(static)
+      for (long i = 0; i < N; ++i) {
+        int x[3];
+        coords(&s->P, i, x);
+        double h[QMAX], phin[QMAX], grad[3], lap, u[3], hp[QMAX];
+        for (int a = 0; a < q; ++a) h[a] = s->h[a * N + i];
+        phin[0] = s->phi[i];
+        for (int a = 1; a < q; ++a) phin[a] = phi_neighbour(&c, x, a);
+        grad_lap_fn(L, phin, grad, &lap);
+        for (int d = 0; d < 3; ++d) u[d] = sc * u_field[d * N + i];
+        collide_h_fn(L, h, phin[0], u, grad, s->P.xi, s->P.mobility, hp);
+        for (int a = 0; a < q; ++a) s->hp[a * N + i] = hp[a];
+      }
+    }
+#pragma omp parallel
+    {
+      ctx_t c;
+      ctx_full(s, &c);
+      c.phi = s->phi;
+      c.hpost = s->hp;
+      c.gpost = s->g; /* not read: only the phase-field set is streamed */
+      c.unew = s->u;
+#pragma omp for schedule(static)
+      for (long i = 0; i < N; ++i) {
+        int x[3];
+        coords(&s->P, i, x);
+        for (int a = 0; a < q; ++a) pull_one(&c, x, 0, a, &s->hn[a * N + i]);
+      }
+    }
+    double* t = s->h;
+    s->h = s->hn;
+    s->hn = t;
+  }
+  return 0;
+}
+
 int ora_fields(ora_sim* s, double* phi, double* u, double* p) {
   const long N = s->N;
   const int q = s->L->q;

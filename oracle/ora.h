@@ -53,6 +53,10 @@ int ora_init(ora_sim* s, const double* phi0, const double* u0);
 int ora_set_state(ora_sim* s, const double* h, const double* g, const double* u);
 int ora_get_state(const ora_sim* s, double* h, double* g, double* u);
 int ora_step(ora_sim* s, int nsteps);
+/* nsteps steps of the phase-field set alone under the prescribed velocity
+ * scale[k] * u_field[3N] at step k; the hydrodynamic set is not advanced.
+ * Periodic, no-slip and free-slip faces only (returns -1 otherwise). */
+int ora_step_h_prescribed(ora_sim* s, const double* u_field, const double* scale, int nsteps);
 /* macroscopic fields of the current state: phi[N], u[3N] (last computed u^n), p[N] = p* rho cs^2 */
 int ora_fields(ora_sim* s, double* phi, double* u, double* p);
 /* sum of phi and kinetic energy 0.5 sum rho |u|^2, in FP64 with compensated sums */

@@ -3,9 +3,10 @@ the same seeded inputs.
 
 Tolerances (FP32 storage and compute, after 1000 steps unless stated):
   max |phi_gpu - phi_oracle| <= 1e-5,
-  max |u_gpu - u_oracle| / max(max |u_oracle|, U_ref) <= 1e-4,
-with U_ref = sigma / mu_H for the drop, sqrt(g L) for Rayleigh-Taylor and u_j
-for jets.  16-bit storage: max |phi_gpu - phi_oracle| <= 1e-3."""
+  max |u_gpu - u_oracle| / max |u_oracle| <= 1e-4
+(the velocity error relative to the oracle field's own largest speed, also
+for the drop at rest, whose speeds are spurious currents of order 1e-5).
+16-bit storage: max |phi_gpu - phi_oracle| <= 1e-3."""
 import sys
 
 import numpy as np
@@ -48,9 +49,11 @@ def _run_oracle(cfg, phi0, u0, steps):
     return o, phi, u, p
 
 
-def _errors(phi_g, u_g, phi_o, u_o, uref):
+def _errors(phi_g, u_g, phi_o, u_o, uref=None):
+    """max |dphi| and the velocity error relative to max |u_oracle| (uref is
+    kept only to name the case's velocity scale in the log)."""
     ephi = np.abs(phi_g - phi_o).max()
-    eu = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), uref)
+    eu = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), 1e-30)
     return ephi, eu
 
 

@@ -85,7 +85,7 @@ def test_walls_300_steps(name):
         s = lbm.Sim(cfg, phi0, u0).set_tile(*tile).step(300)
         phi_g, u_g, _ = s.fields()
         ephi = np.abs(phi_g.cpu().numpy() - phi_o).max()
-        eu = np.abs(u_g.cpu().numpy() - u_o).max() / max(np.abs(u_o).max(), 2e-3)
+        eu = np.abs(u_g.cpu().numpy() - u_o).max() / max(np.abs(u_o).max(), 1e-30)
         _log(f"walls {name} {tile}: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
         assert ephi <= 1e-5 and eu <= 1e-4
 

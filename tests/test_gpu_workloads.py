@@ -66,9 +66,8 @@ def test_laplace3d_copy_parity():
     phi_o, u_o, p_o = o.fields()
     s = lbm.Sim(cfg, phi0, u0).step(500)
     phi_g, u_g, p_g = [t.cpu().numpy().astype(np.float64) for t in s.fields()]
-    uref = cfg["sigma"] / (cfg["rho_h"] * cfg["tau_h"] * CS2)
     ephi = np.abs(phi_g - phi_o).max()
-    eu = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), uref)
+    eu = np.abs(u_g - u_o).max() / max(np.abs(u_o).max(), 1e-30)
     _log(f"laplace3d copy: max|dphi|={ephi:.3e} rel_u={eu:.3e} max|dp|={np.abs(p_g - p_o).max():.3e}")
     assert ephi <= 1e-5 and eu <= 1e-4
 
@@ -160,29 +159,62 @@ def test_rt_case_one_step_every_node(case, n):
         assert eh < 2e-7 and eg < 2e-7 and eu < 2e-7
 
 
+def _fp32_rounded_step(o, n):
+    """n oracle steps, the state rounded to FP32 after each one."""
+    for _ in range(n):
+        o.step(1)
+        h, g, u = o.state()
+        o.set_state(*(a.astype(np.float32).astype(np.float64) for a in (h, g, u)))
+
+
 @pytest.mark.parametrize("case,n,steps", [("a", 32, 1000), ("b", 32, 1000), ("c", 16, 500), ("d", 16, 500)])
 def test_rt_case_copy_trajectory(case, n, steps):
     """The same copies over several hundred steps against the FP64 oracle.
-    The one-step test above shows the step itself agrees to FP32 rounding;
-    over many steps these cases amplify that rounding where the heavy bulk
-    sits slightly off phi = 1 with a vanishing gradient: the interface normal
-    grad phi / |grad phi| is ill-conditioned there and a rounding-level change
-    turns the sharpening term, of size (1 - 4 (phi - 1/2)^2) / xi.  The FP32
-    trajectories stay within 1e-3 of the FP64 one (7e-4 measured)."""
+
+    Inside the interface band (0.02 < phi < 0.98) the FP32 trajectory meets
+    the 1e-5 bar.  In the bulk these cases are ill-conditioned: the weakly
+    compressible flow moves the heavy bulk a few 1e-3 off phi = 1, where the
+    sharpening term acts along the normal of a nearly flat field, and
+    rounding-level differences grow there.  The FP64 oracle whose state is
+    rounded to FP32 after every step shows the same growth, at the same
+    kind of nodes; it sets the bound outside the band (4x its drift, never
+    below 1e-5), and the velocity bound likewise (1e-4 relative, or 4x the
+    rounded run's)."""
     lbm = _lbm()
     cfg, phi0, u0 = W.rt_case(case, n=n)
     phi0, u0 = W.perturb(phi0, u0, 3, 0.01, 1e-4)
     o = oracle.Oracle(cfg).init(phi0, u0)
+    r = oracle.Oracle(cfg).init(phi0, u0)
+    h, g, u = r.state()
+    r.set_state(*(a.astype(np.float32).astype(np.float64) for a in (h, g, u)))
     s = lbm.Sim(cfg, phi0, u0)
-    errs = []
+    e_band, e_all, e_r, eu_g, eu_r, where = [], [], [], [], [], []
     for k in range(4):
         o.step(steps // 4)
+        _fp32_rounded_step(r, steps // 4)
         s.step(steps // 4)
-        phi_o = o.fields()[0]
-        phi_g = s.fields()[0].cpu().numpy().astype(np.float64)
-        errs.append(float(np.abs(phi_g - phi_o).max()))
-    _log(f"rt case {case}: max|dphi| at steps " + " ".join(f"{(k + 1) * steps // 4}:{e:.2e}" for k, e in enumerate(errs)))
-    assert max(errs) <= 1e-3
+        phi_o, u_o, _ = o.fields()
+        phi_r, u_r, _ = r.fields()
+        phi_g, u_g, _ = [t.cpu().numpy().astype(np.float64) for t in s.fields()]
+        d = np.abs(phi_g - phi_o)
+        band = (phi_o > 0.02) & (phi_o < 0.98)
+        e_band.append(float(d[band].max()))
+        e_all.append(float(d.max()))
+        where.append(float(phi_o.reshape(-1)[d.argmax()]))
+        e_r.append(float(np.abs(phi_r - phi_o).max()))
+        umax = np.abs(u_o).max()
+        eu_g.append(float(np.abs(u_g - u_o).max() / umax))
+        eu_r.append(float(np.abs(u_r - u_o).max() / umax))
+    ck = [(k + 1) * steps // 4 for k in range(4)]
+    _log(f"rt case {case}: band max|dphi| " + " ".join(f"{c}:{e:.1e}" for c, e in zip(ck, e_band)))
+    _log(f"rt case {case}: all  max|dphi| " + " ".join(f"{c}:{e:.1e}(phi={w:.4f})"
+                                                      for c, e, w in zip(ck, e_all, where)))
+    _log(f"rt case {case}: FP32-rounded oracle " + " ".join(f"{c}:{e:.1e}" for c, e in zip(ck, e_r)))
+    _log(f"rt case {case}: rel_u gpu " + " ".join(f"{e:.1e}" for e in eu_g)
+         + " rounded oracle " + " ".join(f"{e:.1e}" for e in eu_r))
+    assert max(e_band) <= 1e-5
+    assert max(e_all) <= max(1e-5, 4.0 * max(e_r))
+    assert max(eu_g) <= max(1e-4, 4.0 * max(eu_r))
 
 
 def _front_positions(phi, lref):
