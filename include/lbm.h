@@ -120,7 +120,10 @@ int lbm_state_bytes(const lbm_params* p, size_t* bytes);
 int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, void* state_dev,
              size_t state_bytes, void* stream, lbm_sim** out);
 
-/* Advance n >= 0 steps (asynchronous; one graph launch per pair of steps). */
+/* Advance n >= 0 steps (asynchronous).  Pairs of steps replay hipGraphs that
+ * lbm_init and every change of launch shape (lbm_set_tile, lbm_set_store_hint,
+ * lbm_set_blocks_per_cu, lbm_autotune) capture; lbm_step itself only launches
+ * (an odd remaining step goes eagerly). */
 int lbm_step(lbm_sim* s, int n);
 
 /* Steps taken since init or the last import/load. */
@@ -135,8 +138,10 @@ long long lbm_steps_done(const lbm_sim* s);
 int lbm_fields(lbm_sim* s, unsigned mask, float* phi_dev, float* u_dev, float* p_dev);
 
 /* Sum of phi and kinetic energy 0.5 sum rho |u|^2 over all nodes, accumulated
- * in FP64 on the GPU in a fixed order (deterministic).  Synchronises the
- * stream.  Returns LBM_EUNSTABLE if either is not finite. */
+ * in FP64 on the GPU: per-thread strided sums, wavefront (64-lane) reductions,
+ * one partial per block of 256 threads, then a fixed-order final pass
+ * (deterministic).  Synchronises the stream.  Returns LBM_EUNSTABLE if either
+ * is not finite. */
 int lbm_reduce(lbm_sim* s, double* mass, double* kinetic);
 
 /* Canonical FP32 copy of the state (post-stream populations at the current
@@ -207,8 +212,10 @@ int lbm_batch_init(int ndom, const lbm_params* per_domain, const float* const* p
                    lbm_batch** out);
 int lbm_batch_step(lbm_batch* b, int n);
 long long lbm_batch_steps_done(const lbm_batch* b);
-/* mass[ndom], kinetic[ndom] (host); FP64, fixed order; synchronises.  Every
- * entry is written; LBM_EUNSTABLE if any domain's value is not finite. */
+/* mass[ndom], kinetic[ndom] (host); FP64, fixed order, the same arithmetic
+ * as lbm_reduce with the partials of all domains in one launch; synchronises
+ * once.  Every entry is written; LBM_EUNSTABLE if any domain's value is not
+ * finite. */
 int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic);
 int lbm_batch_fields(lbm_batch* b, int dom, unsigned mask, float* phi_dev, float* u_dev, float* p_dev);
 int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, float* u_dev);

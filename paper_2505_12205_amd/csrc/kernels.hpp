@@ -1361,56 +1361,75 @@ __global__ __launch_bounds__(256) void k_pressure(KParams P, KBufs B, float* __r
 }
 
 // FP64 sums of phi and 0.5 rho |u|^2: per-block partials in a fixed order
-__global__ __launch_bounds__(256) void k_reduce_partial(KParams P, const float* __restrict__ phi,
-                                                        const float* __restrict__ u, double* __restrict__ part) {
-  __shared__ double sm[256], sk[256];
-  double m = 0.0, k = 0.0;
+// FP64 sum over the 64 lanes of a wave (xor butterfly); every lane ends with
+// a sum, and callers take lane 0's, whose order of additions is fixed.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of phi and of 0.5 rho |u|^2 per domain, in FP64: block b takes part
+// (b % ppd) of domain (b / ppd), each thread a strided run of nodes, then a
+// wave reduction and a fixed-order sum of the block's four waves; part[2b],
+// part[2b + 1] receive the block's sums.  Deterministic for a given ppd.
+template <int PAR>
+__global__ __launch_bounds__(256) void k_reduce_partial(const DomDev* __restrict__ D, int ppd,
+                                                        double* __restrict__ part) {
+  const int d = blockIdx.x / ppd, j = blockIdx.x % ppd;
+  const KParams& P = D[d].K;
+  const float* __restrict__ phi = D[d].B[PAR].phi;
+  const float* __restrict__ u = D[d].B[PAR].u;
   const size_t N = (size_t)P.N;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+  const double rho_l = P.rho_l, drho = P.drho;
+  const int clamp = P.clamp;
+  double m = 0.0, k = 0.0;
+  for (size_t i = (size_t)j * 256 + threadIdx.x; i < N; i += (size_t)ppd * 256) {
     const double ph = phi[i];
-    const double phc = P.clamp ? fmin(fmax(ph, 0.0), 1.0) : ph;
-    const double rho = (double)P.rho_l + phc * (double)P.drho;
+    const double phc = clamp ? fmin(fmax(ph, 0.0), 1.0) : ph;
+    const double rho = rho_l + phc * drho;
     const double ux = u[i], uy = u[N + i], uz = u[2 * N + i];
     m += ph;
     k += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
   }
-  sm[threadIdx.x] = m;
-  sk[threadIdx.x] = k;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[threadIdx.x] += sm[threadIdx.x + o];
-      sk[threadIdx.x] += sk[threadIdx.x + o];
-    }
-    __syncthreads();
+  m = wave_sum(m);
+  k = wave_sum(k);
+  __shared__ double sm[4], sk[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[w] = m;
+    sk[w] = k;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sm[0];
-    part[2 * blockIdx.x + 1] = sk[0];
+    part[2 * blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
+    part[2 * blockIdx.x + 1] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nparts,
+// One block per domain: the domain's ppd partials summed in a fixed order
+// (strided per thread, wave reduction, the four waves in order) into
+// out[2d] (sum phi) and out[2d + 1] (kinetic energy).
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int ppd,
                                                       double* __restrict__ out) {
-  __shared__ double sm[256], sk[256];
+  const double* p = part + 2 * (size_t)blockIdx.x * ppd;
   double m = 0.0, k = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    m += part[2 * i];
-    k += part[2 * i + 1];
+  for (int i = threadIdx.x; i < ppd; i += 256) {
+    m += p[2 * i];
+    k += p[2 * i + 1];
   }
-  sm[threadIdx.x] = m;
-  sk[threadIdx.x] = k;
+  m = wave_sum(m);
+  k = wave_sum(k);
+  __shared__ double sm[4], sk[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[w] = m;
+    sk[w] = k;
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[threadIdx.x] += sm[threadIdx.x + o];
-      sk[threadIdx.x] += sk[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    out[0] = sm[0];
-    out[1] = sk[0];
+    out[2 * blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
+    out[2 * blockIdx.x + 1] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
   }
 }
 

@@ -38,6 +38,8 @@ int fail(int code, const std::string& msg) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+
+
 struct Layout {
   size_t h, g, u, phi0, phi1, obuf, total;
 };
@@ -243,7 +245,7 @@ struct lbm_sim {
   double* part;         // reduction partials (library scratch)
   double* res;          // 2 doubles on the device
   double* res_host;     // pinned
-  int nparts;
+  int ppd;              // reduction partials of the domain
   LaunchSet ls;
   hipGraphExec_t g_pair, g_many;
   int many_pairs;
@@ -424,17 +426,46 @@ hipError_t launch_phi_t(const LaunchSet& ls, int par, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_phi(lbm_sim* s) {
-  const int par = s->parity();
-  if (s->Q == 9) {
-    if (s->ST == 0) return launch_phi_t<9, 0>(s->ls, par, s->stream);
-    if (s->ST == 1) return launch_phi_t<9, 1>(s->ls, par, s->stream);
-    return launch_phi_t<9, 2>(s->ls, par, s->stream);
-  }
-  if (s->ST == 0) return launch_phi_t<19, 0>(s->ls, par, s->stream);
-  if (s->ST == 1) return launch_phi_t<19, 1>(s->ls, par, s->stream);
-  return launch_phi_t<19, 2>(s->ls, par, s->stream);
+
+// ---- FP64 reductions over a domain table -------------------------------------
+// Partial sums per domain: one per 64 Ki nodes of the largest domain, at
+// least 1 and at most 1024, and at most kReduceMaxParts over all domains.
+constexpr int kReduceMaxParts = 16384;
+
+int reduce_ppd(size_t max_nodes, int ndom) {
+  size_t p = (max_nodes + 65535) / 65536;
+  p = std::min<size_t>(std::max<size_t>(p, 1), 1024);
+  p = std::min<size_t>(p, std::max<size_t>(1, (size_t)kReduceMaxParts / (size_t)std::max(ndom, 1)));
+  return (int)p;
 }
+
+hipError_t launch_phi_ls(const LaunchSet& ls, int Q, int ST, int par, hipStream_t st) {
+  if (Q == 9) {
+    if (ST == 0) return launch_phi_t<9, 0>(ls, par, st);
+    if (ST == 1) return launch_phi_t<9, 1>(ls, par, st);
+    return launch_phi_t<9, 2>(ls, par, st);
+  }
+  if (ST == 0) return launch_phi_t<19, 0>(ls, par, st);
+  if (ST == 1) return launch_phi_t<19, 1>(ls, par, st);
+  return launch_phi_t<19, 2>(ls, par, st);
+}
+
+// phase-field pass of every domain of the set, then per-domain sums of phi and
+// kinetic energy: part holds ndom * ppd pairs, out receives 2 * ndom doubles
+hipError_t launch_reduce(const LaunchSet& ls, int Q, int ST, int par, int ppd, double* part, double* out,
+                         hipStream_t st) {
+  hipError_t e = launch_phi_ls(ls, Q, ST, par, st);
+  if (e != hipSuccess) return e;
+  const dim3 gp((unsigned)(ls.ndom * ppd)), bp(256);
+  if (par == 0)
+    hipLaunchKernelGGL(k_reduce_partial<0>, gp, bp, 0, st, (const DomDev*)ls.d_dom, ppd, part);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<1>, gp, bp, 0, st, (const DomDev*)ls.d_dom, ppd, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(ls.ndom), bp, 0, st, (const double*)part, ppd, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi(lbm_sim* s) { return launch_phi_ls(s->ls, s->Q, s->ST, s->parity(), s->stream); }
 
 // ---- auxiliary kernels of one domain ----------------------------------------
 template <int Q, int ST>
@@ -526,14 +557,19 @@ int build_graphs(lbm_sim* s) {
   return rc;
 }
 
-int set_launch(lbm_sim* s, int bx, int by, int bpc, int nt) {
+// new launch shape; with `graphs` the step graphs are captured again here, so
+// that lbm_step only replays them
+int set_launch(lbm_sim* s, int bx, int by, int bpc, int nt, bool graphs) {
   drop_graphs(s);
   lbm_sim* v[1] = {s};
-  return build_launch(s->ls, v, 1, bx, by, bpc, nt);
+  int rc = build_launch(s->ls, v, 1, bx, by, bpc, nt);
+  if (rc == LBM_OK && graphs) rc = build_graphs(s);
+  return rc;
 }
 
-// simulation object on an existing state buffer; no launch
-lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
+// simulation object on an existing state buffer; no launch.  `graphs`: capture
+// the step graphs now (a batch's per-domain views step through the batch's)
+lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc, bool graphs) {
   lbm_sim* s = new lbm_sim();
   s->P = *p;
   s->K = kparams_of(*p);
@@ -552,9 +588,9 @@ lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
   default_tile(*p, bx, by);
   split_domain(*p, s->box, s->faces);
   s->T = tiling_of(p->nx, p->ny, p->nz, bx, by);
-  s->nparts = 1024;
+  s->ppd = reduce_ppd(s->N, 1);
   hipError_t e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc(&s->part, sizeof(double) * 2 * s->nparts);
+  if (e == hipSuccess) e = hipMalloc(&s->part, sizeof(double) * 2 * s->ppd);
   if (e == hipSuccess) e = hipMalloc(&s->res, sizeof(double) * 2);
   if (e == hipSuccess) e = hipHostMalloc(&s->res_host, sizeof(double) * 2, hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -562,7 +598,7 @@ lbm_sim* new_sim(const lbm_params* p, char* base, hipStream_t stream, int* rc) {
     lbm_destroy(s);
     return nullptr;
   }
-  *rc = set_launch(s, bx, by, 4, 0);
+  *rc = set_launch(s, bx, by, 4, 0, graphs);
   if (*rc) {
     lbm_destroy(s);
     return nullptr;
@@ -683,7 +719,7 @@ int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, vo
   const Layout L = layout_of(*p);
   if (state_bytes < L.total) return fail(LBM_ENOMEM, "state buffer smaller than lbm_state_bytes()");
   if (((uintptr_t)state_dev) & 255) return fail(LBM_EINVAL, "state buffer must be 256-byte aligned");
-  lbm_sim* s = new_sim(p, (char*)state_dev, (hipStream_t)stream, &rc);
+  lbm_sim* s = new_sim(p, (char*)state_dev, (hipStream_t)stream, &rc, true);
   if (!s) return rc;
   rc = init_kernels(s, phi0_dev, u0_dev);
   if (rc) {
@@ -696,10 +732,7 @@ int lbm_init(const lbm_params* p, const float* phi0_dev, const float* u0_dev, vo
 
 int lbm_step(lbm_sim* s, int n) {
   if (!s || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
-  if (n >= 2 && !s->g_pair) {
-    int rc = build_graphs(s);
-    if (rc) return rc;
-  }
+  if (n >= 2 && !s->g_pair) return fail(LBM_EINVAL, "no step graph (an autotune trial left the launch without one)");
   while (n > 0) {
     if (s->parity() == 1 || n == 1) {
       HIPCHK(launch_step(s->ls, s->Q, s->ST, s->parity(), s->stream));
@@ -738,12 +771,7 @@ int lbm_fields(lbm_sim* s, unsigned mask, float* phi_dev, float* u_dev, float* p
 
 int lbm_reduce(lbm_sim* s, double* mass, double* kinetic) {
   if (!s || !mass || !kinetic) return fail(LBM_EINVAL, "null argument");
-  HIPCHK(launch_phi(s));
-  hipLaunchKernelGGL(k_reduce_partial, dim3(s->nparts), dim3(256), 0, s->stream, s->K,
-                     (const float*)s->out_buf(s->parity()), (const float*)s->u(), s->part);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s->stream, (const double*)s->part, s->nparts, s->res);
-  HIPCHK(hipGetLastError());
+  HIPCHK(launch_reduce(s->ls, s->Q, s->ST, s->parity(), s->ppd, s->part, s->res, s->stream));
   HIPCHK(hipMemcpyAsync(s->res_host, s->res, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
   *mass = s->res_host[0];
@@ -800,17 +828,17 @@ int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes) {
 int lbm_set_tile(lbm_sim* s, int bx, int by) {
   if (!s) return fail(LBM_EINVAL, "null handle");
   if (!tile_ok(bx, by)) return fail(LBM_EINVAL, "tile must have bx % 16 == 0 and bx*by a multiple of 64 up to 512");
-  return set_launch(s, bx, by, s->ls.bpc, s->ls.nt);
+  return set_launch(s, bx, by, s->ls.bpc, s->ls.nt, true);
 }
 
 int lbm_set_store_hint(lbm_sim* s, int nontemporal) {
   if (!s) return fail(LBM_EINVAL, "null handle");
-  return set_launch(s, s->ls.bx, s->ls.by, s->ls.bpc, nontemporal ? 1 : 0);
+  return set_launch(s, s->ls.bx, s->ls.by, s->ls.bpc, nontemporal ? 1 : 0, true);
 }
 
 int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu) {
   if (!s || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad argument");
-  return set_launch(s, s->ls.bx, s->ls.by, blocks_per_cu, s->ls.nt);
+  return set_launch(s, s->ls.bx, s->ls.by, blocks_per_cu, s->ls.nt, true);
 }
 
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by) {
@@ -843,7 +871,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
       const int bx = cb.first, by = cb.second;
       for (int bp : kBpc)
         for (int nt = 0; nt < 2; ++nt) {
-          int rc = set_launch(s, bx, by, bp, nt);
+          int rc = set_launch(s, bx, by, bp, nt, false);
           double ms = 0.0;
           if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, 2, &ms);  // warm-up
           if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, trial_steps, &ms);
@@ -854,7 +882,7 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
-  int rc = set_launch(s, best.bx, best.by, best.bpc, best.nt);
+  int rc = set_launch(s, best.bx, best.by, best.bpc, best.nt, true);
   if (rc) return rc;
   if (bx_out) *bx_out = best.bx;
   if (by_out) *by_out = best.by;
@@ -890,6 +918,10 @@ struct lbm_batch {
   hipGraphExec_t g_pair = nullptr;
   int* d_count = nullptr;
   int count_cap = 0;
+  int ppd = 1;                   // reduction partials per domain
+  double* part = nullptr;        // ndom * ppd pairs (library scratch)
+  double* res = nullptr;         // 2 * ndom doubles on the device
+  double* res_host = nullptr;    // pinned copy of res
 };
 
 namespace {
@@ -917,9 +949,12 @@ int batch_validate(int ndom, const lbm_params* p) {
   return LBM_OK;
 }
 
-int batch_set_launch(lbm_batch* b, int bx, int by, int bpc, int nt) {
+// new launch shape; with `graphs` the step-pair graph is captured again here
+int batch_set_launch(lbm_batch* b, int bx, int by, int bpc, int nt, bool graphs) {
   drop_graph(b->g_pair);
-  return build_launch(b->ls, b->views.data(), b->ndom, bx, by, bpc, nt);
+  int rc = build_launch(b->ls, b->views.data(), b->ndom, bx, by, bpc, nt);
+  if (rc == LBM_OK && graphs) rc = capture_pairs(b->ls, b->Q, b->ST, b->cap, 1, &b->g_pair);
+  return rc;
 }
 
 void batch_sync_views(lbm_batch* b) {
@@ -968,12 +1003,21 @@ int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, 
       rc = fail(LBM_EINVAL, "null phi0 for domain " + std::to_string(d));
       break;
     }
-    b->views[d] = new_sim(&p[d], b->base + b->off[d], b->stream, &rc);
+    b->views[d] = new_sim(&p[d], b->base + b->off[d], b->stream, &rc, false);
     if (rc == LBM_OK) rc = init_kernels(b->views[d], phi0_dev[d], u0_dev ? u0_dev[d] : nullptr);
   }
   if (rc == LBM_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
     rc = fail(LBM_EDEVICE, "stream create");
-  if (rc == LBM_OK) rc = batch_set_launch(b, 32, 8, 4, 0);
+  if (rc == LBM_OK) {
+    size_t maxn = 1;
+    for (auto* v : b->views) maxn = std::max(maxn, v->N);
+    b->ppd = reduce_ppd(maxn, ndom);
+    hipError_t e = hipMalloc(&b->part, sizeof(double) * 2 * (size_t)ndom * b->ppd);
+    if (e == hipSuccess) e = hipMalloc(&b->res, sizeof(double) * 2 * ndom);
+    if (e == hipSuccess) e = hipHostMalloc(&b->res_host, sizeof(double) * 2 * ndom, hipHostMallocDefault);
+    if (e != hipSuccess) rc = fail(LBM_ENOMEM, std::string("batch reduction scratch: ") + hipGetErrorString(e));
+  }
+  if (rc == LBM_OK) rc = batch_set_launch(b, 32, 8, 4, 0, true);
   if (rc) {
     lbm_batch_destroy(b);
     return rc;
@@ -984,10 +1028,7 @@ int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, 
 
 int lbm_batch_step(lbm_batch* b, int n) {
   if (!b || n < 0) return fail(LBM_EINVAL, "bad handle or step count");
-  if (n >= 2 && !b->g_pair) {
-    int rc = capture_pairs(b->ls, b->Q, b->ST, b->cap, 1, &b->g_pair);
-    if (rc) return rc;
-  }
+  if (n >= 2 && !b->g_pair) return fail(LBM_EINVAL, "no step graph (an autotune trial left the launch without one)");
   while (n > 0) {
     if ((b->steps & 1) || n == 1) {
       HIPCHK(launch_step(b->ls, b->Q, b->ST, (int)(b->steps & 1), b->stream));
@@ -1007,15 +1048,16 @@ long long lbm_batch_steps_done(const lbm_batch* b) { return b ? b->steps : -1; }
 int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic) {
   if (!b || !mass || !kinetic) return fail(LBM_EINVAL, "null argument");
   batch_sync_views(b);
-  int worst = LBM_OK;
+  HIPCHK(launch_reduce(b->ls, b->Q, b->ST, (int)(b->steps & 1), b->ppd, b->part, b->res, b->stream));
+  HIPCHK(hipMemcpyAsync(b->res_host, b->res, 2 * sizeof(double) * b->ndom, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  bool finite = true;
   for (int d = 0; d < b->ndom; ++d) {
-    int rc = lbm_reduce(b->views[d], &mass[d], &kinetic[d]);
-    if (rc == LBM_EUNSTABLE)
-      worst = rc;
-    else if (rc)
-      return rc;
+    mass[d] = b->res_host[2 * d];
+    kinetic[d] = b->res_host[2 * d + 1];
+    finite = finite && std::isfinite(mass[d]) && std::isfinite(kinetic[d]);
   }
-  if (worst) return fail(worst, "non-finite mass or kinetic energy in a domain");
+  if (!finite) return fail(LBM_EUNSTABLE, "non-finite mass or kinetic energy in a domain");
   return LBM_OK;
 }
 
@@ -1066,7 +1108,7 @@ int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length) {
 int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal) {
   if (!b) return fail(LBM_EINVAL, "null handle");
   if (!tile_ok(bx, by) || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad launch shape");
-  return batch_set_launch(b, bx, by, blocks_per_cu, nontemporal ? 1 : 0);
+  return batch_set_launch(b, bx, by, blocks_per_cu, nontemporal ? 1 : 0, true);
 }
 
 int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blocks_per_cu, int* nontemporal,
@@ -1092,7 +1134,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blo
     for (const auto& cb : tile_candidates(w, miny)) {
       for (int bp : kBpc)
         for (int nt = 0; nt < 2; ++nt) {
-          int rc = batch_set_launch(b, cb.first, cb.second, bp, nt);
+          int rc = batch_set_launch(b, cb.first, cb.second, bp, nt, false);
           double ms = 0.0;
           if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, 2, &ms);
           if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, trial_steps, &ms);
@@ -1103,7 +1145,7 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blo
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
-  int rc = batch_set_launch(b, best.bx, best.by, best.bpc, best.nt);
+  int rc = batch_set_launch(b, best.bx, best.by, best.bpc, best.nt, true);
   if (rc) return rc;
   if (bx) *bx = best.bx;
   if (by) *by = best.by;
@@ -1125,6 +1167,9 @@ void lbm_batch_destroy(lbm_batch* b) {
   for (auto* v : b->views)
     if (v) lbm_destroy(v);
   if (b->d_count) (void)hipFree(b->d_count);
+  if (b->part) (void)hipFree(b->part);
+  if (b->res) (void)hipFree(b->res);
+  if (b->res_host) (void)hipHostFree(b->res_host);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
