@@ -217,6 +217,18 @@ long long lbm_batch_steps_done(const lbm_batch* b);
  * once.  Every entry is written; LBM_EUNSTABLE if any domain's value is not
  * finite. */
 int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic);
+/* Allocation-free variant of lbm_batch_reduce, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  out_dev: caller-owned device buffer of 2 * ndom doubles;
+ * out_dev[2d] = sum phi and out_dev[2d + 1] = kinetic energy of domain d,
+ * bitwise the values lbm_batch_reduce returns.  Launches on the batch's
+ * stream and returns without synchronising or copying to the host; nothing
+ * is allocated or freed.  The partial sums live in a static device array of
+ * 16384 pairs of doubles (256 KiB on each GPU, held until the process ends),
+ * so ndom > 16384 is rejected with LBM_EINVAL.  All calls on one GPU share
+ * that array: calls that overlap on one GPU (on different streams) race.
+ * Non-finite values are returned as they are. */
+int lbm_batch_reduce_noalloc(lbm_batch* b, double* out_dev);
 int lbm_batch_fields(lbm_batch* b, int dom, unsigned mask, float* phi_dev, float* u_dev, float* p_dev);
 int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, float* u_dev);
 /* Intact liquid length of each domain, length[ndom] (host), in nodes along

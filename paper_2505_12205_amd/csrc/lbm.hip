@@ -38,6 +38,38 @@ int fail(int code, const std::string& msg) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Capacity, in pairs of doubles, of the reduction partials of one launch.
+constexpr int kReduceMaxParts = 16384;
+
+}  // namespace
+
+// Partial sums of the allocation-free batch reduction
+// (lbm_batch_reduce_noalloc): kReduceMaxParts pairs of doubles, 256 KiB on
+// each GPU the library runs on, held until the process ends.  Every call on a
+// GPU shares that GPU's copy, so reductions that overlap on one GPU race.
+static __device__ __align__(256) double scratch[2 * kReduceMaxParts];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // device address of `scratch`, per device ordinal
+
+// Device address of the static scratch array on the current device, looked
+// up once per device (host code must not pass the array's name to a kernel).
+int scratch_on_current_device(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = (double*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_OK;
+}
+
 
 
 struct Layout {
@@ -429,8 +461,9 @@ hipError_t launch_phi_t(const LaunchSet& ls, int par, hipStream_t st) {
 
 // ---- FP64 reductions over a domain table -------------------------------------
 // Partial sums per domain: one per 64 Ki nodes of the largest domain, at
-// least 1 and at most 1024, and at most kReduceMaxParts over all domains.
-constexpr int kReduceMaxParts = 16384;
+// least 1 and at most 1024, and at most kReduceMaxParts over all domains
+// (the capacity of the allocation-free reduction's scratch array).  Both
+// batch reductions use this count, so they give bitwise the same sums.
 
 int reduce_ppd(size_t max_nodes, int ndom) {
   size_t p = (max_nodes + 65535) / 65536;
@@ -922,6 +955,7 @@ struct lbm_batch {
   double* part = nullptr;        // ndom * ppd pairs (library scratch)
   double* res = nullptr;         // 2 * ndom doubles on the device
   double* res_host = nullptr;    // pinned copy of res
+  double* scratch = nullptr;     // this device's copy of the static scratch array
 };
 
 namespace {
@@ -1017,6 +1051,7 @@ int lbm_batch_init(int ndom, const lbm_params* p, const float* const* phi0_dev, 
     if (e == hipSuccess) e = hipHostMalloc(&b->res_host, sizeof(double) * 2 * ndom, hipHostMallocDefault);
     if (e != hipSuccess) rc = fail(LBM_ENOMEM, std::string("batch reduction scratch: ") + hipGetErrorString(e));
   }
+  if (rc == LBM_OK) rc = scratch_on_current_device(&b->scratch);
   if (rc == LBM_OK) rc = batch_set_launch(b, 32, 8, 4, 0, true);
   if (rc) {
     lbm_batch_destroy(b);
@@ -1058,6 +1093,19 @@ int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic) {
     finite = finite && std::isfinite(mass[d]) && std::isfinite(kinetic[d]);
   }
   if (!finite) return fail(LBM_EUNSTABLE, "non-finite mass or kinetic energy in a domain");
+  return LBM_OK;
+}
+
+int lbm_batch_reduce_noalloc(lbm_batch* b, double* out_dev) {
+  if (!b || !out_dev) return fail(LBM_EINVAL, "null argument");
+  if (b->ndom > kReduceMaxParts)
+    return fail(LBM_EINVAL, "lbm_batch_reduce_noalloc: at most " + std::to_string(kReduceMaxParts) +
+                                " domains (the static scratch holds that many partial sums)");
+  if ((size_t)b->ndom * b->ppd > (size_t)kReduceMaxParts)
+    return fail(LBM_EINVAL, "lbm_batch_reduce_noalloc: partial sums exceed the static scratch");
+  if (!b->scratch) return fail(LBM_EDEVICE, "static scratch address not resolved on this device");
+  batch_sync_views(b);
+  HIPCHK(launch_reduce(b->ls, b->Q, b->ST, (int)(b->steps & 1), b->ppd, b->scratch, out_dev, b->stream));
   return LBM_OK;
 }
 

@@ -77,6 +77,7 @@ def _load():
     L.lbm_batch_steps_done.argtypes = [vp]
     L.lbm_batch_steps_done.restype = C.c_longlong
     L.lbm_batch_reduce.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.lbm_batch_reduce_noalloc.argtypes = [vp, vp]
     L.lbm_batch_fields.argtypes = [vp, C.c_int, C.c_uint, vp, vp, vp]
     L.lbm_batch_export_state.argtypes = [vp, C.c_int, vp, vp, vp]
     L.lbm_batch_intact_length.argtypes = [vp, C.c_float, C.POINTER(C.c_int)]
@@ -97,7 +98,7 @@ EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fi
             "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_blocks_per_cu", "lbm_autotune",
             "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version",
             "lbm_batch_state_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_steps_done",
-            "lbm_batch_reduce", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
+            "lbm_batch_reduce", "lbm_batch_reduce_noalloc", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
             "lbm_batch_set_launch", "lbm_batch_autotune", "lbm_batch_kernel_times", "lbm_batch_destroy")
 
 
@@ -346,6 +347,15 @@ class Batch:
         if rc != LBM_EUNSTABLE or strict:
             _check(rc)
         return list(m), list(k)
+
+    def reduce_noalloc(self, out):
+        """Allocation-free reduction into a caller device tensor out (float64,
+        2 * ndom entries): out[2d] = sum phi, out[2d + 1] = kinetic energy.
+        Asynchronous on the batch's stream."""
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < 2 * self.ndom:
+            raise ValueError("out must be a contiguous float64 device tensor of 2 * ndom entries")
+        _check(lib.lbm_batch_reduce_noalloc(self._h, out.data_ptr()))
+        return out
 
     def fields(self, dom: int):
         sh = self.shapes[dom]
