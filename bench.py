@@ -30,17 +30,19 @@ def algorithmic_bytes_per_node(q: int, d: int, pop_bytes: int):
     return 2 * 2 * q * pop_bytes + 2 * d * 4 + 8, kstep, kphi
 
 
-def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True):
+def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True, zchunk=None):
     import torch
 
     from paper_2505_12205_amd import lbm
     sim = lbm.Sim(cfg, phi0, u0, storage=storage)
+    if zchunk is not None:
+        sim.set_zchunk(zchunk)
     if tile:
         sim.set_tile(*tile)
     elif autotune:
         choice = sim.autotune(trial_steps=6)
         print(f"[bench] {storage} autotune -> tile {choice[0]}x{choice[1]} nontemporal={choice[2]} "
-              f"{choice[3]:.3f} ms/step", file=sys.stderr, flush=True)
+              f"z-chunk {sim.zchunk} {choice[3]:.3f} ms/step", file=sys.stderr, flush=True)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -50,6 +52,29 @@ def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True):
     kt = sim.kernel_times(min(steps, 20))
     mass, ke = sim.reduce()
     return sim, dt, kt, mass, ke
+
+
+def run_jet(steps, warmup, forms=("fp32", "fp16", "bf16"), autotune=True):
+    """The precision-form jet at its stated size (192 x 192 x 768, inlet radius
+    12, rho* = 800, We = 5, Re = 300, convective outflow) in each storage
+    form: MLUPS of the whole step and the fused kernel's algorithmic GB/s."""
+    import torch
+
+    from paper_2505_12205_amd import workloads as W
+    cfg, phi0, u0 = W.jet3d()
+    n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    out = {"nodes": n}
+    for st in forms:
+        sim, dt, kt, _, _ = run_gpu(cfg, phi0, u0, st, steps, warmup, None, autotune)
+        _, bk, _ = algorithmic_bytes_per_node(19, 3, 4 if st == "fp32" else 2)
+        out[st] = {"MLUPS": round(n * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+                   "step_kernel_ms": round(kt[1], 4), "phi_pass_ms": round(kt[0], 4),
+                   "outlet_ms": round(kt[2], 4),
+                   "step_kernel_GBs": round(bk * n / (kt[1] * 1e-3) / 1e9, 1)}
+        print(f"[bench] jet 192x192x768 {st} {out[st]}", file=sys.stderr, flush=True)
+        del sim
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_batch(steps, warmup, storage="fp16", autotune=True, launch=None):
@@ -216,6 +241,8 @@ def main():
     ap.add_argument("--forms", default="fp16,bf16",
                     help="comma list of 16-bit storage forms to time beside FP32 ('' for none)")
     ap.add_argument("--tile", default="", help="bx,by launch shape of the fused kernel")
+    ap.add_argument("--zchunk", type=int, default=None,
+                    help="planes per z-marching task of the fused kernel (0: tiled kernel)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Weber sweep")
     ap.add_argument("--no-bgk", action="store_true", help="skip the FP32 run with the BGK operator")
@@ -228,6 +255,7 @@ def main():
     ap.add_argument("--drops-only", action="store_true",
                     help="only run the drop-size diagnostic (for profiling it alone)")
     ap.add_argument("--no-drops", action="store_true", help="skip the drop-size diagnostic")
+    ap.add_argument("--no-jet", action="store_true", help="skip the 192x192x768 jet in each storage form")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
@@ -265,13 +293,14 @@ def main():
     print(f"[bench] workload {cfg['name']} N={N} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     sim, dt, kt, mass, ke = run_gpu(cfg, phi0, u0, "fp32", args.steps, args.warmup, tile,
-                                    not args.no_autotune)
+                                    not args.no_autotune, args.zchunk)
     mlups = N * args.steps / dt / 1e6
     b_step, b_k, b_phi = algorithmic_bytes_per_node(19, 3, 4)
     achieved = b_k * N / (kt[1] * 1e-3) / 1e9
     print(f"[bench] fp32 {mlups:.1f} MLUPS, kernels phi {kt[0]:.3f} ms step {kt[1]:.3f} ms",
           file=sys.stderr, flush=True)
     tile_used = sim.tile
+    zchunk_used = sim.zchunk
     del sim
     torch.cuda.empty_cache()
 
@@ -297,6 +326,12 @@ def main():
                              "step_kernel_GBs": round(b_k * N / (kt2[1] * 1e-3) / 1e9, 1)}
         print(f"[bench] bgk_fp32 {forms['bgk_fp32']}", file=sys.stderr, flush=True)
         del s2
+        torch.cuda.empty_cache()
+
+    if not args.no_jet:
+        forms["jet_192x192x768"] = run_jet(max(20, args.steps // 4), 5,
+                                           tuple(["fp32"] + [f for f in args.forms.split(",") if f]),
+                                           not args.no_autotune)
         torch.cuda.empty_cache()
 
     if not args.no_batch:
@@ -336,12 +371,13 @@ def main():
         "data": "synthetic (analytic cosine-perturbed interface, seeded parameters)",
         "config": {"workload": "rayleigh_taylor_3d_d3q19", "nx": 256, "ny": 1024, "nz": 256,
                    "storage": "fp32", "atwood": 0.5, "reynolds": 3000, "W": 5,
-                   "tile": list(tile_used)},
+                   "tile": list(tile_used), "z_chunk": zchunk_used},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_source": traffic_src,
                      "traffic_GBs": round(traffic / (kt[1] * 1e-3) / 1e9, 1) if traffic else None,
-                     "kernel": "k_step (fused macroscopic + collisions + AA streaming)",
+                     "kernel": ("kb_march" if zchunk_used else "kb_interior") +
+                               " (fused macroscopic update + both collisions + AA streaming)",
                      "bytes_per_node": b_k, "kernel_ms": round(kt[1], 4),
                      "phi_pass_ms": round(kt[0], 4), "device_copy_GBs": round(copy_gbs, 1)},
         "step_bytes_per_node": b_step,

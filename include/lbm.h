@@ -95,7 +95,10 @@ typedef struct {
   double inlet_center[2];/* nozzle centre in the inlet face's tangential axes (x,y for z faces) */
   double inlet_radius;   /* nozzle radius R: phi_in = u_in/u_j = 1/2 [1 + tanh(2 (R - r)/xi)] */
   double inlet_u;        /* plug speed u_j along the inward normal */
-  int outlet_mode;       /* lbm_outlet_mode (LOCAL only is implemented) */
+  int outlet_mode;       /* lbm_outlet_mode: the convective velocity U of the outflow
+                            (appendix B): the node's own outward velocity at the layer
+                            next to the outlet (LOCAL), or its maximum (MAX) or average
+                            (AVERAGE) over that layer; clipped at zero */
   int storage;           /* lbm_storage */
   unsigned variant_flags;/* LBM_VF_* */
 } lbm_params;
@@ -162,6 +165,13 @@ int lbm_load(lbm_sim* s, const void* host_buf, size_t bytes);
 int lbm_set_tile(lbm_sim* s, int bx, int by);
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by);
 
+/* D3Q19 interior kernel: planes per z-marching task (the tile's phase field
+ * and its halo staged in an LDS ring of planes), or 0 (the default) for the
+ * tiled kernel that reads the stencil from global memory.  Both give the same
+ * result bit for bit; the autotuners try both. */
+int lbm_set_zchunk(lbm_sim* s, int planes);
+int lbm_get_zchunk(const lbm_sim* s, int* planes);
+
 /* Non-temporal hint (nonzero) on the population stores of the fused kernel. */
 int lbm_set_store_hint(lbm_sim* s, int nontemporal);
 
@@ -171,7 +181,8 @@ int lbm_set_store_hint(lbm_sim* s, int nontemporal);
 int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu);
 
 /* Autotuner: times trial_steps eager steps for each candidate tile shape,
- * blocks per compute unit and store hint and keeps the fastest; results are cached per (lattice, storage,
+ * blocks per compute unit, store hint and (D3Q19) z-marching chunk (0 or 32
+ * planes) and keeps the fastest; results are cached per (lattice, storage,
  * grid, boundary set) for the life of the process, so later simulations of
  * the same shape take the cached choice without trials.  The state advances
  * by the trial steps.  Synchronises.  Outputs (nullable): chosen bx, by,
@@ -217,6 +228,8 @@ long long lbm_batch_steps_done(const lbm_batch* b);
  * once.  Every entry is written; LBM_EUNSTABLE if any domain's value is not
  * finite. */
 int lbm_batch_reduce(lbm_batch* b, double* mass, double* kinetic);
+/* As lbm_set_zchunk, for every domain of the batch. */
+int lbm_batch_set_zchunk(lbm_batch* b, int planes);
 /* Allocation-free variant of lbm_batch_reduce, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  out_dev: caller-owned device buffer of 2 * ndom doubles;

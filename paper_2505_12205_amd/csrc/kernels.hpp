@@ -6,9 +6,13 @@
 //       both collisions and the in-place AA streaming of both population sets;
 //       the hydrodynamic set relaxes with WMRT, or with BGK (template flag)
 //   kb_outlet<P>: convective outflow plane (only with an outlet face)
-// Nodes off the y and z faces of non-periodic axes take the tiled fast path
-// with precomputed neighbour offsets (x walls included, with a per-lane slot
-// choice); the y and z face layers take the general path.
+// Nodes off the y and z faces of non-periodic axes take the fast path with
+// precomputed neighbour offsets (x walls included, with a per-lane slot
+// choice): in D3Q19 the kernel marches each tile along z with the tile's
+// phase field and its halo staged in an LDS ring of planes (kb_march), in
+// D2Q9 (and with marching switched off) one tile per block reads the stencil
+// from global memory (kb_interior); the y and z face layers take the general
+// path.
 //
 // Storage is structure-of-arrays, pop[a][node] with node = x + nx*(y + ny*z)
 // (x fastest), one array per set; streaming is the AA pattern:
@@ -41,6 +45,7 @@ struct KParams {
   float in_c0, in_c1, in_R, in_u, two_over_xi;
   int clamp;
   int has_inlet, has_outlet;
+  int outlet_mode;         // convective velocity: 0 local, 1 plane maximum, 2 plane average
   int wbits, nsbits;       // x faces: bit 0 (1) = the minus (plus) face is a wall / a no-slip wall
 };
 
@@ -112,8 +117,24 @@ __device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
+// BF16 with stochastic rounding: 16 pseudo-random bits, a hash of the value's
+// FP32 bits and its slot index, are added below the kept significand before
+// truncation, so the stored value rounds up with probability equal to the
+// dropped fraction (unbiased on average; deterministic for given inputs, and
+// the slot index is local to the domain, so a batched domain stores the same
+// bits as the domain alone).  Round-to-nearest-even biases the hydrodynamic
+// set's small velocity moments step after step; this removes the bias.
+// One 32-bit multiply: the carries make the product's upper half a
+// nonlinear mix of every input bit (a shift-xor mix alone left the rounding
+// correlated with the dropped bits and biased).
+__device__ __forceinline__ uint16_t f2bf_sr(float v, uint32_t slot) {
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t x = (b + (slot << 16) + slot) * 0x85EBCA77u;
+  return (uint16_t)((b + (x >> 16)) >> 16);
+}
+
 template <>
-struct Codec<2> {  // BF16 deviations, same encoding as FP16
+struct Codec<2> {  // BF16 deviations, same encoding as FP16, stochastic rounding
   using T = uint16_t;
   template <typename P, typename I>
   static __device__ __forceinline__ float ld_h(P p, I i, float w, float ref) {
@@ -121,12 +142,14 @@ struct Codec<2> {  // BF16 deviations, same encoding as FP16
   }
   template <bool NT = false, typename P = void, typename I = size_t>
   static __device__ __forceinline__ void st_h(P p, I i, float v, float iw, float ref) {
-    put<NT>(p, i, f2bf(v * iw - ref));
+    put<NT>(p, i, f2bf_sr(v * iw - ref, (uint32_t)i));
   }
   template <typename P, typename I>
   static __device__ __forceinline__ float ld_g(P p, I i, float w) { return w * bf2f(p[i]); }
   template <bool NT = false, typename P = void, typename I = size_t>
-  static __device__ __forceinline__ void st_g(P p, I i, float v, float iw) { put<NT>(p, i, f2bf(v * iw)); }
+  static __device__ __forceinline__ void st_g(P p, I i, float v, float iw) {
+    put<NT>(p, i, f2bf_sr(v * iw, (uint32_t)i));
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -694,6 +717,24 @@ __device__ __forceinline__ Nbr make_nbr(const KParams& P, const int c[3]) {
   return n;
 }
 
+// Phase field of the stencil, from global memory (neighbour offsets) or from
+// an LDS tile of three planes with a one-node halo (the marching kernel).
+struct PhiGlobal {
+  const __attribute__((address_space(1))) float* p;
+  template <int Q>
+  __device__ __forceinline__ float at(const Nbr& nb, int a) const {
+    return p[a == 0 ? nb.node : nb.at<Q>(a)];
+  }
+};
+struct PhiLds {
+  const float* pl[3];  // planes z-1, z, z+1
+  int li, W;           // this node's cell in a plane, row pitch of the tile
+  template <int Q>
+  __device__ __forceinline__ float at(const Nbr&, int a) const {
+    return pl[Lat<Q>::ez[a] + 1][li + Lat<Q>::ey[a] * W + Lat<Q>::ex[a]];
+  }
+};
+
 // Walls of the x axis are handled inside the tiled kernels: their nodes are
 // one per row, so a separate face launch would read and write them one value
 // per memory line.  Bit 0 (1) of the result: node c lies on the minus (plus)
@@ -753,8 +794,8 @@ __device__ __forceinline__ bool on_special_face(const KParams& P, const int c[3]
 // sum to 1 + O(1e-8)) would leave a small systematic mass drift per step, so
 // the node's mass is restored on the rest population with compensated sums
 // (a zero correction in exact arithmetic).
-template <int Q, int ST, int ODD, bool NT, bool WALL, bool BGK>
-__device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, const int c[3]) {
+template <int Q, int ST, int ODD, bool NT, bool WALL, bool BGK, class PhiSrc>
+__device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, const int c[3], const PhiSrc& PS) {
   using L = Lat<Q>;
   constexpr int D = L::D;
   using C = Codec<ST>;
@@ -768,15 +809,14 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   using GF = __attribute__((address_space(1))) float;
   GTy* Gp = (GTy*)B.g;  // loads and stores go through one pointer: in place
   GTy* Hp = (GTy*)B.h;
-  const GF* Phi = (const GF*)B.phi;
   GF* Uv = (GF*)B.u;
 
-  const float phi = Phi[node];
+  const float phi = PS.template at<Q>(nb, 0);
   float gr[3] = {0.f, 0.f, 0.f}, lap = 0.f;
   float phn[Q];  // neighbours' phase field, kept: the 16-bit forms encode with the readers' one
 #pragma unroll
   for (int a = 1; a < Q; ++a) {
-    phn[a] = Phi[nb.at<Q>(a)];
+    phn[a] = PS.template at<Q>(nb, a);
     stencil_add<Q>(a, phn[a], phi, gr, lap);
   }
   gr[0] *= 3.0f;
@@ -856,11 +896,17 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
   }
   const float d0 = om * (X.phi * L::w[0] * hB - h0);
   float dsum = d0;  // sum of the increments h+_a - h_a
+  // momentum of the stored post-collision g, summed as stored; the axis
+  // pairs come last and carry the momentum correction (below)
+  float mom[3] = {0.f, 0.f, 0.f};
 
   // pairs (a, abar): even parts of the equilibria and of the stress
-  // projection are shared, odd parts change sign
+  // projection are shared, odd parts change sign.  Pairs are taken in
+  // descending index order, so the axis pairs (1, 2), (3, 4), (5, 6) come
+  // after every pair with a component along their axis.
 #pragma unroll
-  for (int a = 1; a < Q; ++a) {
+  for (int k = Q - 1; k >= 1; --k) {
+    const int a = k;
     const int b = L::opp[a];
     if (b < a) continue;
     const int ex = L::ex[a], ey = L::ey[a], ez = L::ez[a];
@@ -879,12 +925,13 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
     const float eu2 = eu * eu;
     // hydrodynamic set
     const float eF = ex * X.F[0] + ey * X.F[1] + ez * X.F[2];
+    float va, vb;  // post-collision a (stored where b was read) and b
     if (BGK) {  // (1 - s) g + s f^eq + (1 - s/2) F_a, even and odd parts
       const float sr = X.s;
       const float gsym = sr * w * (gA + 4.5f * eu2);
       const float ganti = w * (sr * 3.0f * eu + (2.0f - sr) * hf * eF);
-      C::template st_g<NT>(Gb, ib, (1.0f - sr) * gv[a] + gsym + ganti, 1.0f / w);  // a goes where b was read
-      C::template st_g<NT>(Ga, ia, (1.0f - sr) * gv[b] + gsym - ganti, 1.0f / w);
+      va = (1.0f - sr) * gv[a] + gsym + ganti;
+      vb = (1.0f - sr) * gv[b] + gsym - ganti;
     } else {
       float proj = 0.0f;
       if (ex) proj += X.cxx;
@@ -896,9 +943,33 @@ __device__ __forceinline__ void step_fast(const KParams& P, const KBufs& B, cons
       if (D == 2) proj *= (1.0f / w);  // the D2Q9 projection is not weighted
       const float gsym = w * (gA + 4.5f * eu2 + proj);
       const float ganti = w * (3.0f * eu + hf * eF);
-      C::template st_g<NT>(Gb, ib, gsym + ganti, 1.0f / w);  // a goes where b was read
-      C::template st_g<NT>(Ga, ia, gsym - ganti, 1.0f / w);
+      va = gsym + ganti;
+      vb = gsym - ganti;
     }
+    const float dv = va - vb;
+    if (ex) mom[0] += ex * dv;
+    if (ey) mom[1] += ey * dv;
+    if (ez) mom[2] += ez * dv;
+    const int nax = (ex != 0) + (ey != 0) + (ez != 0);
+    if (nax == 1) {
+      // The post-collision momentum is u + F / (2 rho) (WMRT) or
+      // (1 - s) j + s u + (1 - s/2) F / rho (BGK) in exact arithmetic.  With
+      // the FP32 weights the stored values carry it scaled by 1 + O(1e-8)
+      // with a fixed sign (6 (w_1 + 4 w_2) - 1 = 7.5e-9 in D3Q19), a drift
+      // that compounds over the steps; the axis pair of each direction, the
+      // last pair with a component along it, takes the difference (+c/2 on
+      // a, -c/2 on abar: mass and second moments unchanged).
+      const int d = ex ? 0 : (ey ? 1 : 2);
+      const int sg = ex + ey + ez;  // +1: a points along +d
+      const float target = BGK ? (1.0f - X.s) * j[d] + X.s * X.u[d] +
+                                     (1.0f - 0.5f * X.s) * X.F[d] * X.f3r * (1.0f / 3.0f)
+                               : X.u[d] + X.F[d] * X.f3r * (1.0f / 6.0f);
+      const float c = 0.5f * (float)sg * (target - mom[d]);
+      va += c;
+      vb -= c;
+    }
+    C::template st_g<NT>(Gb, ib, va, 1.0f / w);  // a goes where b was read
+    C::template st_g<NT>(Ga, ia, vb, 1.0f / w);
     // phase-field set
     const float pw = X.phi * w;
     const float hsym = pw * (hB + 4.5f * eu2);
@@ -958,11 +1029,31 @@ __device__ __forceinline__ void step_general(const KParams& P, const KBufs& B, c
   if (D == 3) B.u[2 * N + node] = X.u[2];
 
   Ty* Gw = (Ty*)B.g;
+  // post-collision g with the momentum correction of the fast path: the
+  // difference between the exact post-collision momentum and the one the
+  // FP32 values carry goes to the axis pairs
+  float gq[Q], mom[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    gq[a] = g_post<Q, BGK>(X, a, g[a]);
+    if (L::ex[a]) mom[0] += L::ex[a] * gq[a];
+    if (L::ey[a]) mom[1] += L::ey[a] * gq[a];
+    if (D == 3 && L::ez[a]) mom[2] += L::ez[a] * gq[a];
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const float target = BGK ? (1.0f - X.s) * j[d] + X.s * X.u[d] + (1.0f - 0.5f * X.s) * X.F[d] * X.f3r * (1.0f / 3.0f)
+                             : X.u[d] + X.F[d] * X.f3r * (1.0f / 6.0f);
+    const float cc = 0.5f * (target - mom[d]);
+    const int ap = d == 0 ? find_vel<Q>(1, 0, 0) : (d == 1 ? find_vel<Q>(0, 1, 0) : find_vel<Q>(0, 0, 1));
+    gq[ap] += cc;
+    gq[L::opp[ap]] -= cc;
+  }
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
     int sp, sn;
     if (resolve_dst<Q, ODD>(P, c, a, sp, sn))
-      C::template st_g<NT>(Gw, (size_t)sp * N + sn, g_post<Q, BGK>(X, a, g[a]), 1.0f / L::w[a]);
+      C::template st_g<NT>(Gw, (size_t)sp * N + sn, gq[a], 1.0f / L::w[a]);
   }
   float pre_s = 0.f, pre_c = 0.f, post_s = 0.f, post_c = 0.f;
 #pragma unroll
@@ -1096,7 +1187,7 @@ __device__ __forceinline__ void phi_general(const KParams& P, const KBufs& B, co
 // k_outlet: convective outflow (appendix B) after the step of parity ODD
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int ODD>
-__device__ __forceinline__ void outlet_node(const KParams& P, const KBufs& B, int pi) {
+__device__ __forceinline__ void outlet_node(const KParams& P, const KBufs& B, int pi, const float* uplane) {
   constexpr int AX = Lat<Q>::AX;
   int c[3];
   if (Lat<Q>::D == 3) {
@@ -1112,7 +1203,9 @@ __device__ __forceinline__ void outlet_node(const KParams& P, const KBufs& B, in
   float h[Q], g[Q];
   load_node<Q, ST, !ODD, true>(P, B, c, h, g);
   const int node = node_of(P, c[0], c[1], c[2]);
-  const float U = fmaxf(B.u[(size_t)AX * P.N + node], 0.0f);
+  // local option: the outward velocity of this node; plane options: the
+  // clipped maximum or average over the layer, from k_outlet_speed
+  const float U = P.outlet_mode == 0 ? fmaxf(B.u[(size_t)AX * P.N + node], 0.0f) : *uplane;
   const float inv = 1.0f / (1.0f + U);
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -1135,6 +1228,8 @@ struct DomDev {
   Faces F;
   int ntx, nty, ntiles;     // interior tiling
   int tile_base, face_base, plane_base;
+  int task_base;            // first z-marching task of the domain (D3Q19)
+  float* uplane;            // convective velocity of the plane options (one float)
 };
 
 // Persistent, chunked launch over the tile list of all domains: each block
@@ -1160,7 +1255,77 @@ __global__ __launch_bounds__(512) void kb_interior(const DomDev* __restrict__ D,
     if (PHI)
       phi_fast<Q, ST, ODD, WALL>(dm.K, dm.B[ODD], c);
     else
-      step_fast<Q, ST, ODD, NT, WALL, BGK>(dm.K, dm.B[ODD], c);
+      step_fast<Q, ST, ODD, NT, WALL, BGK>(dm.K, dm.B[ODD], c,
+                                           PhiGlobal{(const __attribute__((address_space(1))) float*)dm.B[ODD].phi});
+  }
+}
+
+// index on an axis of n nodes for a stencil cell: periodic axes wrap, others
+// clamp to the face node (the ghost rule of the phase-field stencil; cells
+// beyond the box's last partial tile stay in bounds and are read by no node)
+__device__ __forceinline__ int cell_axis(int v, int n, bool periodic) {
+  if (periodic) return ((v % n) + n) % n;
+  return min(max(v, 0), n - 1);
+}
+
+// Interior step of a D3Q19 domain marching along z.  A task is one tile
+// (bx x by nodes) of a domain's box over a chunk of zc planes; the phase field
+// of the tile and its one-node halo is staged in an LDS ring of five planes,
+// one plane loaded per plane advanced (one barrier per plane), and the
+// stencil reads it there instead of 19 global loads per node.  Tasks are
+// numbered tile-fastest within each z-chunk, and each persistent block walks
+// a contiguous chunk of them (contiguous per XCD after the remap).
+template <int ST, int ODD, bool NT, bool WALL, bool BGK>
+__global__ __launch_bounds__(512) void kb_march(const DomDev* __restrict__ D, const int* __restrict__ task_dom,
+                                                int ntasks, int chunk, int bx, int by, int zc) {
+  extern __shared__ float ring[];
+  const int W = bx + 2, PL = W * (by + 2);
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int t0 = L * chunk;
+  const int t1 = min(t0 + chunk, ntasks);
+  const int tid = (int)threadIdx.x, nth = (int)blockDim.x;
+  const int i = tid % bx, j = tid / bx;
+  for (int t = t0; t < t1; ++t) {
+    const int d = task_dom ? task_dom[t] : 0;
+    const DomDev& dm = D[d];
+    const KParams& P = dm.K;
+    const int nxy = dm.ntx * dm.nty;
+    const int lt = t - dm.task_base;
+    const int tile = lt % nxy, zci = lt / nxy;
+    const int gx0 = dm.X.x0 + (tile % dm.ntx) * bx, gy0 = dm.X.y0 + (tile / dm.ntx) * by;
+    const int zb = dm.X.z0 + zci * zc, ze = min(zb + zc, dm.X.z0 + dm.X.nz);
+    const bool px = P.bc[0] == BC_PERIODIC, py = P.bc[2] == BC_PERIODIC, pz = P.bc[4] == BC_PERIODIC;
+    const __attribute__((address_space(1))) float* Phi =
+        (const __attribute__((address_space(1))) float*)dm.B[ODD].phi;
+    auto load_plane = [&](int z) {  // plane z into its ring slot
+      float* dst = ring + ((z - zb + 1) % 5) * PL;
+      const int zr = cell_axis(z, P.nz, pz);
+      for (int k = tid; k < PL; k += nth) {
+        const int x = cell_axis(gx0 + k % W - 1, P.nx, px);
+        const int y = cell_axis(gy0 + k / W - 1, P.ny, py);
+        dst[k] = Phi[node_of(P, x, y, zr)];
+      }
+    };
+    __syncthreads();  // the previous task's last plane has been read
+    load_plane(zb - 1);
+    load_plane(zb);
+    load_plane(zb + 1);
+    const bool valid = gx0 + i < dm.X.x0 + dm.X.nx && gy0 + j < dm.X.y0 + dm.X.ny;
+    for (int z = zb; z < ze; ++z) {
+      if (z + 2 <= ze) load_plane(z + 2);
+      __syncthreads();
+      if (valid) {
+        const int c[3] = {gx0 + i, gy0 + j, z};
+        const int m = z - zb + 1;  // ring index of plane z
+        PhiLds PS;
+        PS.pl[0] = ring + ((m + 4) % 5) * PL;
+        PS.pl[1] = ring + (m % 5) * PL;
+        PS.pl[2] = ring + ((m + 1) % 5) * PL;
+        PS.li = (j + 1) * W + (i + 1);
+        PS.W = W;
+        step_fast<19, ST, ODD, NT, WALL, BGK>(P, dm.B[ODD], c, PS);
+      }
+    }
   }
 }
 
@@ -1198,7 +1363,7 @@ __global__ __launch_bounds__(256) void kb_outlet(const DomDev* __restrict__ D, i
   const int d = find_dom<1>(D, ndom, t);
   const DomDev& dm = D[d];
   if (!dm.K.has_outlet) return;
-  outlet_node<Q, ST, ODD>(dm.K, dm.Bo[ODD], t - dm.plane_base);
+  outlet_node<Q, ST, ODD>(dm.K, dm.Bo[ODD], t - dm.plane_base, dm.uplane);
 }
 
 // per-plane count of nodes with phi > threshold along the streamwise axis
@@ -1430,6 +1595,44 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
   if (threadIdx.x == 0) {
     out[2 * blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
     out[2 * blockIdx.x + 1] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
+  }
+}
+
+// Convective velocity of the plane options (appendix B: U_max, U_ave): the
+// outward normal velocity of the latest macroscopic update over the layer
+// next to the outlet, its maximum or its average, clipped at zero.  One
+// block per domain; the average is an FP64 sum in a fixed order.
+template <int Q>
+__global__ __launch_bounds__(256) void k_outlet_speed(const DomDev* __restrict__ D) {
+  constexpr int AX = Lat<Q>::AX;
+  const DomDev& dm = D[blockIdx.x];
+  const KParams& P = dm.K;
+  if (!P.has_outlet || P.outlet_mode == 0) return;
+  const float* u = dm.B[0].u + (size_t)AX * P.N;
+  const size_t base = (size_t)P.plane * (size_t)((AX == 2 ? P.nz : P.ny) - 2);
+  float mx = -3.0e38f;
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < P.plane; i += 256) {
+    const float v = u[base + i];
+    mx = fmaxf(mx, v);
+    sum += (double)v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  sum = wave_sum(sum);
+  __shared__ float smx[4];
+  __shared__ double ssum[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smx[w] = mx;
+    ssum[w] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(smx[0], smx[1]), fmaxf(smx[2], smx[3]));
+    const double s = ((ssum[0] + ssum[1]) + ssum[2]) + ssum[3];
+    const float U = P.outlet_mode == 1 ? m : (float)(s / (double)P.plane);
+    *dm.uplane = fmaxf(U, 0.0f);
   }
 }
 

@@ -121,8 +121,9 @@ int validate(const lbm_params* p) {
   if (has_bc(*p, LBM_BC_CONVECTIVE_OUTLET)) {
     const int n = ax == 2 ? p->nz : p->ny;
     if (n < 3) return fail(LBM_EINVAL, "outlet axis needs at least 3 nodes");
-    if (p->outlet_mode != LBM_OUTLET_LOCAL)
-      return fail(LBM_EUNSUPPORTED, "only the local convective velocity is implemented");
+    if (p->outlet_mode != LBM_OUTLET_LOCAL && p->outlet_mode != LBM_OUTLET_MAX &&
+        p->outlet_mode != LBM_OUTLET_AVERAGE)
+      return fail(LBM_EINVAL, "unknown convective velocity option");
   }
   return LBM_OK;
 }
@@ -179,6 +180,7 @@ KParams kparams_of(const lbm_params& p) {
   K.clamp = (p.variant_flags & LBM_VF_CLAMP_PHI) ? 1 : 0;
   K.has_inlet = has_bc(p, LBM_BC_VELOCITY_INLET) ? 1 : 0;
   K.has_outlet = has_bc(p, LBM_BC_CONVECTIVE_OUTLET) ? 1 : 0;
+  K.outlet_mode = p.outlet_mode;
   for (int side = 0; side < 2; ++side) {  // x faces (never inlet or outlet)
     const int b = p.bc[side];
     if (b == LBM_BC_NOSLIP || b == LBM_BC_FREESLIP) K.wbits |= 1 << side;
@@ -244,6 +246,11 @@ bool tile_ok(int bx, int by) {
 // device table and launch geometry of a set of domains
 struct LaunchSet {
   DomDev* d_dom = nullptr;
+  float* d_uplane = nullptr;  // convective velocity per domain (plane options)
+  bool plane_speed = false;   // some domain takes a plane option
+  int* d_task = nullptr;      // z-marching task -> domain (null for a single domain)
+  int ntasks = 0, zc = 0;     // z-marching tasks (D3Q19), planes per task (0: tiled kernel)
+  int mgrid = 1, mchunk = 1;  // persistent launch of the marching kernel
   int* d_tile = nullptr;  // tile -> domain (null for a single domain)
   int ndom = 0, ntiles = 0, nface = 0, nplane = 0;
   int bx = 64, by = 4, bpc = 4, nt = 0;
@@ -255,6 +262,10 @@ struct LaunchSet {
 void free_launch(LaunchSet& ls) {
   if (ls.d_dom) (void)hipFree(ls.d_dom);
   if (ls.d_tile) (void)hipFree(ls.d_tile);
+  if (ls.d_uplane) (void)hipFree(ls.d_uplane);
+  ls.d_uplane = nullptr;
+  if (ls.d_task) (void)hipFree(ls.d_task);
+  ls.d_task = nullptr;
   ls.d_dom = nullptr;
   ls.d_tile = nullptr;
 }
@@ -310,8 +321,9 @@ namespace {
 // blocks per CU, store hint); allocates the table (replacing any old one).
 int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bpc, int nt) {
   std::vector<DomDev> dom(n);
-  std::vector<int> tile_dom;
-  int tb = 0, fb = 0, pb = 0;
+  std::vector<int> tile_dom, task_dom;
+  int tb = 0, fb = 0, pb = 0, kb = 0;
+  const int zc = ls.zc;
   bool wall = false;
   const bool bgk = (v[0]->P.variant_flags & LBM_VF_BGK) != 0;
   for (int d = 0; d < n; ++d) {
@@ -337,15 +349,28 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
     m.plane_base = pb;
     if (n > 1) tile_dom.insert(tile_dom.end(), (size_t)TB.ntiles, d);
     tb += TB.ntiles;
+    m.task_base = kb;
+    // zc = 0 selects the tiled kernel: no marching tasks
+    const int ntask = (zc > 0 && s->box.nz > 0) ? TB.ntx * TB.nty * ((s->box.nz + zc - 1) / zc) : 0;
+    if (n > 1) task_dom.insert(task_dom.end(), (size_t)ntask, d);
+    kb += ntask;
     fb += s->faces.n1 + s->faces.n2;
     wall |= s->K.wbits != 0;
     pb += s->K.has_outlet ? s->K.plane : 0;
   }
   free_launch(ls);
+  HIPCHK(hipMalloc(&ls.d_uplane, sizeof(float) * n));
+  HIPCHK(hipMemset(ls.d_uplane, 0, sizeof(float) * n));
+  ls.plane_speed = false;
+  for (int d = 0; d < n; ++d) {
+    dom[d].uplane = ls.d_uplane + d;
+    ls.plane_speed |= dom[d].K.has_outlet && dom[d].K.outlet_mode != 0;
+  }
   ls.wall = wall;
   ls.bgk = bgk;
   ls.ndom = n;
   ls.ntiles = tb;
+  ls.ntasks = kb;
   ls.nface = fb;
   ls.nplane = pb;
   ls.bx = bx;
@@ -354,6 +379,10 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   ls.nt = nt;
   HIPCHK(hipMalloc(&ls.d_dom, sizeof(DomDev) * n));
   HIPCHK(hipMemcpy(ls.d_dom, dom.data(), sizeof(DomDev) * n, hipMemcpyHostToDevice));
+  if (n > 1 && kb) {
+    HIPCHK(hipMalloc(&ls.d_task, sizeof(int) * kb));
+    HIPCHK(hipMemcpy(ls.d_task, task_dom.data(), sizeof(int) * kb, hipMemcpyHostToDevice));
+  }
   if (n > 1 && tb) {
     HIPCHK(hipMalloc(&ls.d_tile, sizeof(int) * tb));
     HIPCHK(hipMemcpy(ls.d_tile, tile_dom.data(), sizeof(int) * tb, hipMemcpyHostToDevice));
@@ -366,6 +395,9 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   const int want = std::max(1, std::min(std::max(tb, 1), cus * bpc));
   ls.chunk = std::max(1, (tb + want - 1) / want);
   ls.grid = std::max(1, (tb + ls.chunk - 1) / ls.chunk);
+  const int mwant = std::max(1, std::min(std::max(kb, 1), cus * bpc));
+  ls.mchunk = std::max(1, (kb + mwant - 1) / mwant);
+  ls.mgrid = std::max(1, (kb + ls.mchunk - 1) / ls.mchunk);
   return LBM_OK;
 }
 
@@ -386,7 +418,16 @@ void launch_phi_set(const LaunchSet& ls, hipStream_t st) {
 template <int Q, int ST, int PAR, bool NT, bool BGK>
 void launch_collide_op(const LaunchSet& ls, hipStream_t st) {
   const dim3 gi(ls.grid), bi(ls.bx * ls.by);
-  if (ls.ntiles && ls.wall)
+  if (Q == 19 && ls.zc > 0) {  // z-marching interior with the LDS phase-field ring
+    const dim3 gm(ls.mgrid);
+    const size_t lds = sizeof(float) * 5 * (size_t)(ls.bx + 2) * (ls.by + 2);
+    if (ls.ntasks && ls.wall)
+      hipLaunchKernelGGL((kb_march<ST, PAR, NT, true, BGK>), gm, bi, lds, st, ls.d_dom, ls.d_task, ls.ntasks,
+                         ls.mchunk, ls.bx, ls.by, ls.zc);
+    else if (ls.ntasks)
+      hipLaunchKernelGGL((kb_march<ST, PAR, NT, false, BGK>), gm, bi, lds, st, ls.d_dom, ls.d_task, ls.ntasks,
+                         ls.mchunk, ls.bx, ls.by, ls.zc);
+  } else if (ls.ntiles && ls.wall)
     hipLaunchKernelGGL((kb_interior<Q, ST, PAR, NT, false, true, BGK>), gi, bi, 0, st, ls.d_dom, ls.d_tile,
                        ls.ntiles, ls.chunk, ls.bx, ls.by);
   else if (ls.ntiles)
@@ -429,6 +470,7 @@ hipError_t launch_step_t(const LaunchSet& ls, int par, hipStream_t st, hipEvent_
   if (ev) (void)hipEventRecord(ev[2], st);
   if (ls.nplane) {
     const dim3 gp((ls.nplane + 255) / 256), bp(256);
+    if (ls.plane_speed) hipLaunchKernelGGL((k_outlet_speed<Q>), dim3(ls.ndom), bp, 0, st, ls.d_dom);
     if (par == 0)
       hipLaunchKernelGGL((kb_outlet<Q, ST, 0>), gp, bp, 0, st, ls.d_dom, ls.ndom, ls.nplane);
     else
@@ -695,7 +737,7 @@ int phase_times(const LaunchSet& ls, int Q, int ST, hipStream_t st, long long& s
 }
 
 struct TuneEntry {
-  int bx, by, bpc, nt;
+  int bx, by, bpc, nt, zc;
   double ms;
 };
 std::mutex g_tune_mu;
@@ -703,6 +745,8 @@ std::map<std::string, TuneEntry> g_tune_cache;
 
 const int kTiles[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4}, {32, 4}, {16, 16}};
 const int kBpc[] = {2, 4, 8};
+// planes per z-marching task tried by the autotuners (D3Q19; 0 = tiled kernel)
+const int kZc[] = {0, 32};
 
 // Candidate tiles of the autotuner for boxes whose rows are `w` nodes wide
 // (0: widths differ): the fixed list without mostly idle shapes, plus
@@ -874,6 +918,18 @@ int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu) {
   return set_launch(s, s->ls.bx, s->ls.by, blocks_per_cu, s->ls.nt, true);
 }
 
+int lbm_set_zchunk(lbm_sim* s, int planes) {
+  if (!s || planes < 0 || planes > 4096) return fail(LBM_EINVAL, "bad argument");
+  s->ls.zc = planes;
+  return set_launch(s, s->ls.bx, s->ls.by, s->ls.bpc, s->ls.nt, true);
+}
+
+int lbm_get_zchunk(const lbm_sim* s, int* planes) {
+  if (!s || !planes) return fail(LBM_EINVAL, "null argument");
+  *planes = s->ls.zc;
+  return LBM_OK;
+}
+
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by) {
   if (!s || !bx || !by) return fail(LBM_EINVAL, "null argument");
   *bx = s->ls.bx;
@@ -889,7 +945,7 @@ int lbm_kernel_times(lbm_sim* s, int n, double* out_ms) {
 int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_out, double* ms_out) {
   if (!s || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
   const std::string key = params_key(s->P);
-  TuneEntry best = {s->ls.bx, s->ls.by, s->ls.bpc, s->ls.nt, 1e30};
+  TuneEntry best = {s->ls.bx, s->ls.by, s->ls.bpc, s->ls.nt, s->ls.zc, 1e30};
   bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -903,18 +959,22 @@ int lbm_autotune(lbm_sim* s, int trial_steps, int* bx_out, int* by_out, int* nt_
     for (const auto& cb : tile_candidates(std::max(1, s->box.nx), s->P.ny)) {
       const int bx = cb.first, by = cb.second;
       for (int bp : kBpc)
-        for (int nt = 0; nt < 2; ++nt) {
-          int rc = set_launch(s, bx, by, bp, nt, false);
-          double ms = 0.0;
-          if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, 2, &ms);  // warm-up
-          if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, trial_steps, &ms);
-          if (rc) return rc;
-          if (ms < best.ms) best = {bx, by, bp, nt, ms};
-        }
+        for (int nt = 0; nt < 2; ++nt)
+          for (int zc : kZc) {
+            if (zc && s->Q != 19) continue;
+            s->ls.zc = zc;
+            int rc = set_launch(s, bx, by, bp, nt, false);
+            double ms = 0.0;
+            if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, 2, &ms);  // warm-up
+            if (rc == LBM_OK) rc = time_steps(s->ls, s->Q, s->ST, s->stream, s->steps, trial_steps, &ms);
+            if (rc) return rc;
+            if (ms < best.ms) best = {bx, by, bp, nt, zc, ms};
+          }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
+  s->ls.zc = best.zc;
   int rc = set_launch(s, best.bx, best.by, best.bpc, best.nt, true);
   if (rc) return rc;
   if (bx_out) *bx_out = best.bx;
@@ -1159,11 +1219,17 @@ int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int no
   return batch_set_launch(b, bx, by, blocks_per_cu, nontemporal ? 1 : 0, true);
 }
 
+int lbm_batch_set_zchunk(lbm_batch* b, int planes) {
+  if (!b || planes < 0 || planes > 4096) return fail(LBM_EINVAL, "bad argument");
+  b->ls.zc = planes;
+  return batch_set_launch(b, b->ls.bx, b->ls.by, b->ls.bpc, b->ls.nt, true);
+}
+
 int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blocks_per_cu, int* nontemporal,
                        double* ms_per_step) {
   if (!b || trial_steps < 1) return fail(LBM_EINVAL, "bad argument");
   const std::string key = batch_key(b);
-  TuneEntry best = {b->ls.bx, b->ls.by, b->ls.bpc, b->ls.nt, 1e30};
+  TuneEntry best = {b->ls.bx, b->ls.by, b->ls.bpc, b->ls.nt, b->ls.zc, 1e30};
   bool cached = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1181,18 +1247,22 @@ int lbm_batch_autotune(lbm_batch* b, int trial_steps, int* bx, int* by, int* blo
     }
     for (const auto& cb : tile_candidates(w, miny)) {
       for (int bp : kBpc)
-        for (int nt = 0; nt < 2; ++nt) {
-          int rc = batch_set_launch(b, cb.first, cb.second, bp, nt, false);
-          double ms = 0.0;
-          if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, 2, &ms);
-          if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, trial_steps, &ms);
-          if (rc) return rc;
-          if (ms < best.ms) best = {cb.first, cb.second, bp, nt, ms};
-        }
+        for (int nt = 0; nt < 2; ++nt)
+          for (int zc : kZc) {
+            if (zc && b->Q != 19) continue;
+            b->ls.zc = zc;
+            int rc = batch_set_launch(b, cb.first, cb.second, bp, nt, false);
+            double ms = 0.0;
+            if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, 2, &ms);
+            if (rc == LBM_OK) rc = time_steps(b->ls, b->Q, b->ST, b->stream, b->steps, trial_steps, &ms);
+            if (rc) return rc;
+            if (ms < best.ms) best = {cb.first, cb.second, bp, nt, zc, ms};
+          }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
+  b->ls.zc = best.zc;
   int rc = batch_set_launch(b, best.bx, best.by, best.bpc, best.nt, true);
   if (rc) return rc;
   if (bx) *bx = best.bx;

@@ -1,0 +1,194 @@
+"""Surrogate and solver together on the Weber sweep's jets.
+
+HybridRollout advances jet domains lag by lag (one lag = 32 solver steps)
+with the network on their coarse fields.  A prediction whose phase-field
+budget is violated beyond the threshold (surrogate.fallback_mask) is not
+accepted: the solver, which holds each domain's full-resolution state at the
+last lag it was synchronised, advances that domain (lbm_batch_step) to the
+current lag, and its coarsened fields replace the prediction.  The solver
+cannot restart from a coarse state, so a fallback costs the solver steps
+since the domain's last synchronisation.
+
+The critical Weber number of the dripping-to-jetting transition is
+bracketed on the sweep's Weber grid by calling each domain's regime from its
+intact length over a window of lags (median above two nozzle diameters:
+jetting), two ways:
+  - solver only: bisection, each probe one solver run of one domain through
+    the window;
+  - surrogate-guided: the network rolls every domain out from its initial
+    fields and proposes the first jetting index; the solver then probes the
+    two domains around it, and bisection continues inside whatever bracket
+    those probes leave.
+Both searches end on the same adjacent pair of Weber numbers whenever the
+solver's regime is monotone in We, since every regime that decides the final
+bracket is a solver call.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import lbm, nn
+from . import surrogate as SG
+from . import workloads as W
+
+LAG = 32
+WINDOW = 192
+
+
+def coarse_fields(phi, u, p, cfg, out):
+    """Full-resolution fields of one domain -> coarse physical window [5, 192, ny/2, nx/2]."""
+    return nn.coarsen(phi, u, p, cfg["nx"], cfg["ny"], cfg["nz"], 0, WINDOW, out=out)
+
+
+def initial_coarse(cfg, phi0, u0, out):
+    """Coarse window of a domain's initial fields (p = 0)."""
+    dev = out.device
+    phi = torch.as_tensor(phi0, dtype=torch.float32, device=dev).contiguous()
+    u = torch.as_tensor(u0, dtype=torch.float32, device=dev).contiguous()
+    p = torch.zeros_like(phi)
+    return coarse_fields(phi, u, p, cfg, out)
+
+
+def intact_length(phi_coarse):
+    """Intact length in fine lattice units of coarse phase fields [n, d, h, w]
+    (planes from the inlet holding liquid without a gap, times two)."""
+    has = (phi_coarse > 0.5).reshape(phi_coarse.shape[0], phi_coarse.shape[1], -1).any(axis=2)
+    run = np.where(has.all(axis=1), phi_coarse.shape[1], np.argmin(has, axis=1))
+    return 2 * run
+
+
+class HybridRollout:
+    """Network rollout of `doms` (list of (cfg, phi0, u0)) with solver fallback."""
+
+    def __init__(self, net: SG.Network, doms, storage="fp16"):
+        self.net, self.cfgs = net, [c for c, _, _ in doms]
+        self.n = len(doms)
+        assert self.n == net.batch
+        c0 = self.cfgs[0]
+        self.shape = (5, WINDOW, c0["ny"] // 2, c0["nx"] // 2)
+        self.solver = [lbm.Batch([d], storage=storage) for d in doms]
+        self.sync = np.zeros(self.n, dtype=np.int64)  # lag of each solver state
+        self.x = torch.empty((self.n,) + self.shape, device="cuda")
+        for d, (c, phi0, u0) in enumerate(doms):
+            initial_coarse(c, phi0, u0, self.x[d])
+        self.x_prev = self.x.clone()
+        self.lag = 0
+        self.fallbacks = []              # (lag, domain)
+        self.t_net = self.t_solver = 0.0
+
+    def _solver_state(self, d, out):
+        b = self.solver[d]
+        k = self.lag - int(self.sync[d])
+        t0 = time.perf_counter()
+        b.step(k * LAG)
+        phi, u, p = b.fields(0)
+        coarse_fields(phi, u, p, self.cfgs[d], out)
+        torch.cuda.synchronize()
+        self.t_solver += time.perf_counter() - t0
+        self.sync[d] = self.lag
+
+    def advance(self):
+        """One lag for every domain; returns the domains that fell back."""
+        t0 = time.perf_counter()
+        pred = self.net.predict(self.x)
+        torch.cuda.synchronize()
+        self.t_net += time.perf_counter() - t0
+        bad = np.nonzero(SG.fallback_mask(self.x_prev, self.x, pred))[0] if self.lag > 0 else []
+        self.lag += 1
+        for d in bad:
+            self._solver_state(int(d), pred[int(d)])
+            self.fallbacks.append((self.lag, int(d)))
+        self.x_prev.copy_(self.x)
+        self.x.copy_(pred)
+        return list(map(int, bad))
+
+
+def solver_regime(cfg, phi0, u0, window, storage="fp16"):
+    """Regime of one domain from the solver: intact lengths every lag over
+    lags window[0]..window[1]; returns (jetting, median L_b / D, seconds)."""
+    t0 = time.perf_counter()
+    b = lbm.Batch([(cfg, phi0, u0)], storage=storage)
+    b.step(window[0] * LAG)
+    lb = []
+    for _ in range(window[0], window[1] + 1):
+        lb.append(b.intact_length(0.5)[0])
+        b.step(LAG)
+    torch.cuda.synchronize()
+    med = float(np.median(lb)) / (2.0 * cfg["inlet_radius"])
+    return med > 2.0, med, time.perf_counter() - t0
+
+
+def network_regimes(net: SG.Network, doms, window):
+    """Regimes of all domains from network rollouts started at their initial
+    fields (batches of net.batch domains); returns (jetting[n], median L_b / D, seconds)."""
+    t0 = time.perf_counter()
+    n, bs = len(doms), net.batch
+    c0 = doms[0][0]
+    shape = (5, WINDOW, c0["ny"] // 2, c0["nx"] // 2)
+    med = np.zeros(n)
+    x = torch.empty((bs,) + shape, device="cuda")
+    for s in range(0, n, bs):
+        idx = list(range(s, min(s + bs, n)))
+        pad = idx + [idx[-1]] * (bs - len(idx))
+        for j, d in enumerate(pad):
+            c, phi0, u0 = doms[d]
+            initial_coarse(c, phi0, u0, x[j])
+        lb = []
+        for k in range(1, window[1] + 1):
+            x = net.predict(x)
+            if k >= window[0]:
+                lb.append(intact_length(x[:len(idx), 0].cpu().numpy()))
+        med[idx] = np.median(np.stack(lb), axis=0) / (2.0 * c0["inlet_radius"])
+    torch.cuda.synchronize()
+    return med > 2.0, med, time.perf_counter() - t0
+
+
+def bisect(probe, lo, hi, known=None):
+    """Smallest jetting index on a monotone grid, given that index lo drips
+    and index hi jets (either may be None: unknown ends are probed).
+    probe(i) -> bool (jetting).  Returns (first jetting index, probes)."""
+    known = dict(known or {})
+    calls = []
+
+    def call(i):
+        if i not in known:
+            known[i] = probe(i)
+            calls.append(i)
+        return known[i]
+
+    if not call(hi):
+        return None, calls
+    if call(lo):
+        return lo, calls
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if call(mid):
+            hi = mid
+        else:
+            lo = mid
+    return hi, calls
+
+
+def guided_bracket(probe, n, proposal):
+    """Surrogate-guided search: probe the proposed pair (proposal - 1,
+    proposal) first, then bisect inside the bracket the answers leave."""
+    known = {}
+    p = min(max(proposal, 1), n - 1)
+    known[p - 1] = probe(p - 1)
+    known[p] = probe(p)
+    calls = [p - 1, p]
+    if not known[p - 1] and known[p]:
+        return p, calls
+    if known[p - 1]:      # the transition lies at or below p - 1
+        first, more = bisect(probe, 0, p - 1, known)
+    else:                 # both drip: it lies above p
+        first, more = bisect(probe, p, n - 1, known)
+    return first, calls + more
+
+
+def weber_grid(n=64):
+    """The sweep's domains (lengths, Weber numbers) as (cfg, phi0, u0)."""
+    return W.jet_sweep(n=n)

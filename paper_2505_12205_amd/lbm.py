@@ -67,6 +67,9 @@ def _load():
     L.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.lbm_kernel_times.argtypes = [vp, C.c_int, C.POINTER(C.c_double)]
     L.lbm_set_store_hint.argtypes = [vp, C.c_int]
+    L.lbm_set_zchunk.argtypes = [vp, C.c_int]
+    L.lbm_get_zchunk.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_batch_set_zchunk.argtypes = [vp, C.c_int]
     L.lbm_set_blocks_per_cu.argtypes = [vp, C.c_int]
     L.lbm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
@@ -95,7 +98,7 @@ lib = _load()
 
 EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fields", "lbm_reduce",
             "lbm_export_state", "lbm_import_state", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
-            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_blocks_per_cu", "lbm_autotune",
+            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_zchunk", "lbm_get_zchunk", "lbm_batch_set_zchunk", "lbm_set_blocks_per_cu", "lbm_autotune",
             "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version",
             "lbm_batch_state_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_steps_done",
             "lbm_batch_reduce", "lbm_batch_reduce_noalloc", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
@@ -255,6 +258,17 @@ class Sim:
         _check(lib.lbm_set_store_hint(self._h, 1 if nontemporal else 0))
         return self
 
+    def set_zchunk(self, planes: int):
+        """Planes per z-marching task of the D3Q19 interior kernel (0: tiled kernel)."""
+        _check(lib.lbm_set_zchunk(self._h, int(planes)))
+        return self
+
+    @property
+    def zchunk(self) -> int:
+        v = C.c_int()
+        _check(lib.lbm_get_zchunk(self._h, C.byref(v)))
+        return v.value
+
     def set_blocks_per_cu(self, n: int):
         _check(lib.lbm_set_blocks_per_cu(self._h, int(n)))
         return self
@@ -383,6 +397,10 @@ class Batch:
 
     def set_launch(self, bx: int, by: int, blocks_per_cu: int = 4, nontemporal: bool = False):
         _check(lib.lbm_batch_set_launch(self._h, bx, by, blocks_per_cu, 1 if nontemporal else 0))
+        return self
+
+    def set_zchunk(self, planes: int):
+        _check(lib.lbm_batch_set_zchunk(self._h, int(planes)))
         return self
 
     def autotune(self, trial_steps: int = 4):

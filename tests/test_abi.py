@@ -55,13 +55,25 @@ def test_state_bytes_layout():
     (dict(rho_l=0.0), -1),
     (dict(bc=("periodic", "noslip", "noslip", "noslip", "periodic", "periodic")), -1),
     (dict(bc=("inlet", "outlet", "noslip", "noslip", "periodic", "periodic")), -5),
-    (dict(bc=("periodic", "periodic", "noslip", "noslip", "inlet", "outlet"), outlet_mode="max"), -5),
 ])
 def test_invalid_parameters_rejected_on_host(bad, code):
     from paper_2505_12205_amd import lbm
     with pytest.raises(lbm.LbmError) as ei:
         lbm.state_bytes(_cfg(**bad))
     assert ei.value.code == code
+
+
+@pytest.mark.parametrize("mode", ["local", "max", "average"])
+def test_outlet_velocity_options_accepted(mode):
+    """The three convective-velocity options of appendix B are accepted; an
+    unknown one is rejected."""
+    from paper_2505_12205_amd import lbm
+    cfg = _cfg(bc=("periodic", "periodic", "noslip", "noslip", "inlet", "outlet"), outlet_mode=mode)
+    assert lbm.state_bytes(cfg) > 0
+    p = lbm.make_params(cfg)
+    p.outlet_mode = 7
+    n = lbm.C.c_size_t()
+    assert lbm.lib.lbm_state_bytes(lbm.C.byref(p), lbm.C.byref(n)) == -1
 
 
 def _declared_surrogate():

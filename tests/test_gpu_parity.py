@@ -126,9 +126,8 @@ def test_jet_copy_16bit_storage(storage):
     ephi, eu = _errors(phi_g, u_g, phi_o, u_o, cfg["inlet_u"])
     ep = np.abs(p_g - p_o).max()
     _log(f"jet copy {storage}: max|dphi|={ephi:.3e} rel_u={eu:.3e} max|dp|={ep:.3e}")
-    # FP16 deviations meet the 1e-3 bar; BF16 (8 significant bits) does not
-    # (about 7e-3 after 1000 steps) and is held to a regression bound.
-    assert ephi <= (1e-3 if storage == "fp16" else 2e-2)
+    # both 16-bit forms meet the 1e-3 bar (BF16 through stochastic rounding)
+    assert ephi <= 1e-3
 
 
 def test_drop2d_16bit_storage():
@@ -138,8 +137,7 @@ def test_drop2d_16bit_storage():
         _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 1000, storage=storage)
         ephi, eu = _errors(phi_g, u_g, phi_o, u_o, 1e-3)
         _log(f"drop2d {storage}: max|dphi|={ephi:.3e} rel_u={eu:.3e}")
-        if storage == "fp16":
-            assert ephi <= 1e-3
+        assert ephi <= 1e-3
 
 
 def test_one_step_both_parities_against_oracle_at_every_node():
@@ -293,3 +291,120 @@ def test_rest_and_uniform_flow_are_fixed_points(storage):
     du = np.abs(u.cpu().numpy() - u0).max()
     _log(f"[gpu] uniform flow {storage}: max|u-u0|={du:.2e}")
     assert du <= (1e-6 if storage == "fp32" else 2e-5)
+
+
+@pytest.mark.parametrize("mode", ["max", "average"])
+def test_jet_copy_outlet_plane_options(mode):
+    """Convective outflow with the plane options of appendix B (U_max and
+    U_ave over the layer next to the outlet instead of each node's own
+    outward velocity), 400 steps, FP32, against the oracle; the option must
+    change the run (compared with the local option in the oracle)."""
+    cfg, phi0, u0 = _jet_copy(seed=3)
+    cfg = dict(cfg, outlet_mode=mode)
+    _, phi_o, u_o, _ = _run_oracle(cfg, phi0, u0, 400)
+    _, phi_l, u_l, _ = _oracle_cached("jet_local_400", dict(cfg, outlet_mode="local"), phi0, u0, 400)
+    _, phi_g, u_g, _ = _run_gpu(cfg, phi0, u0, 400)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o)
+    dlocal = np.abs(u_o - u_l).max() / np.abs(u_o).max()
+    _log(f"jet copy outlet {mode}: max|dphi|={ephi:.3e} rel_u={eu:.3e} (option vs local: {dlocal:.2e})")
+    assert dlocal > 1e-6
+    assert ephi <= 1e-5 and eu <= 1e-4
+
+
+def test_drop2d_fp32_2000_steps_and_laplace():
+    """The 2D drop workload at its stated 2000 steps: FP32 parity with the
+    oracle and the Laplace law on the GPU's own pressure field, dp = sigma / R
+    within 5% (mean p inside r < R - 2 xi minus mean p outside r > R + 2 xi).
+
+    Past 1000 steps the drop's centre is ill-conditioned: the heavy bulk sits
+    1e-5 off phi = 1 with a vanishing gradient at the symmetry point, where
+    the sharpening term's direction is undefined, and the FP64 oracle with
+    its state rounded to FP32 after every step drifts by 1.7e-5 there by step
+    2000.  The phase field is therefore held to 1e-5 inside the interface band
+    (0.02 < phi < 0.98) and to four times that rounded oracle's drift in the
+    bulk.  The velocities are spurious currents that decay (max |u| 9.8e-6 at
+    1000 steps, 3.1e-6 at 2000) while FP32 rounding of the velocity sums stays
+    about 5e-10: the velocity error is bounded by 1e-4 of the run's velocity
+    scale, the spurious speed at 1000 steps, i.e. 1e-9."""
+    cfg, phi0, u0 = W.drop2d()
+    _, phi_o, u_o, _ = _oracle_cached("drop2000", cfg, phi0, u0, 2000)
+    r = oracle.Oracle(cfg).init(phi0, u0)
+    for _ in range(2000):
+        r.step(1)
+        h, g, u = r.state()
+        r.set_state(*(a.astype(np.float32).astype(np.float64) for a in (h, g, u)))
+    env = np.abs(r.fields()[0] - phi_o).max()
+    _, phi_g, u_g, p_g = _run_gpu(cfg, phi0, u0, 2000)
+    ephi, eu = _errors(phi_g, u_g, phi_o, u_o)
+    band = (phi_o > 0.02) & (phi_o < 0.98)
+    eband = np.abs(phi_g - phi_o)[band].max()
+    du = np.abs(u_g - u_o).max()
+    n, R = cfg["nx"], 25.0
+    y, x = np.mgrid[0:n, 0:n]
+    rr = np.hypot(x - n / 2, y - n / 2)
+    dp = p_g[0][rr < R - 2 * cfg["xi"]].mean() - p_g[0][rr > R + 2 * cfg["xi"]].mean()
+    lap = dp / (cfg["sigma"] / R) - 1.0
+    _log(f"drop2d 2000 steps: max|dphi|={ephi:.3e} (band {eband:.3e}, FP32-rounded oracle {env:.3e}) "
+         f"max|du|={du:.3e} (rel_u={eu:.3e}) Laplace dp R/sigma - 1 = {lap:+.4f}")
+    assert eband <= 1e-5 and ephi <= max(1e-5, 4.0 * env)
+    assert du <= 1e-4 * 9.8e-6
+    assert abs(lap) < 0.05
+
+
+@pytest.mark.timeout(900)
+def test_jet_config3_parity_copy_64x64x256():
+    """The precision-form jet's stated parity copy: 64 x 64 x 256 with the
+    full jet's nozzle radius 12 and per-node parameters (u_j, sigma, tau, M,
+    W, g), seeded perturbation, 1000 steps against the FP64 oracle, compared
+    every 250 steps: FP32 within 1e-5 in phi and 1e-4 in velocity; FP16 and
+    BF16 deviation storage within 1e-3 in phi (velocity and pressure errors
+    logged, and where the largest phase-field error sits)."""
+    lbm = _lbm()
+    cfg, phi0, u0 = W.jet3d(nx=64, ny=64, nz=256, radius=12.0, stub=16.0)
+    phi0, u0 = W.perturb(phi0, u0, 3, 0.01, 1e-3)
+    _log("[oracle] jet 64x64x256, 1000 steps")
+    o = oracle.Oracle(cfg).init(phi0, u0)
+    sims = {st: lbm.Sim(cfg, phi0, u0, storage=st) for st in ("fp32", "fp16", "bf16")}
+    tol = {"fp32": 1e-5, "fp16": 1e-3, "bf16": 1e-3}
+    worst = {st: 0.0 for st in sims}
+    for k in range(4):
+        o.step(250)
+        phi_o, u_o, p_o = o.fields()
+        for st, s in sims.items():
+            s.step(250)
+            phi_g, u_g, p_g = [t.cpu().numpy().astype(np.float64) for t in s.fields()]
+            ephi, eu = _errors(phi_g, u_g, phi_o, u_o)
+            ep = np.abs(p_g - p_o).max() / np.abs(p_o).max()
+            d = np.abs(phi_g - phi_o)
+            at = np.unravel_index(d.argmax(), d.shape)
+            _log(f"jet 64x64x256 {st} step {250 * (k + 1)}: max|dphi|={ephi:.3e} at (z,y,x)={tuple(map(int, at))} "
+                 f"phi={phi_o[at]:.4f} rel_u={eu:.3e} rel_p={ep:.3e}")
+            worst[st] = max(worst[st], ephi)
+            if st == "fp32":
+                assert eu <= 1e-4
+    for st in sims:
+        assert worst[st] <= tol[st], (st, worst[st])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("which", ["rt", "jet"])
+def test_z_marching_kernel_equals_tiled_kernel(which, storage):
+    """The D3Q19 interior kernel marching along z with the phase field staged
+    in LDS gives bit for bit the state of the tiled kernel that reads the
+    stencil from global memory, for several chunk lengths and tiles (ragged
+    last chunk, partial tiles, wall lanes and inlet/outlet faces in the jet)."""
+    lbm = _lbm()
+    if which == "rt":
+        cfg, phi0, u0 = _rt_copy(37, 29, 23, seed=5)
+    else:
+        cfg, phi0, u0 = _jet_copy(nx=24, ny=20, nz=37, seed=3)
+    ref = lbm.Sim(cfg, phi0, u0, storage=storage).set_zchunk(0).step(25)
+    h0, g0, u_0 = [t.cpu().numpy() for t in ref.export_state()]
+    for zc, tile in ((16, None), (5, (32, 8)), (1, (64, 4)), (64, (16, 16))):
+        _log(f"[gpu] z-marching {which} {storage} zc={zc} tile={tile}")
+        s = lbm.Sim(cfg, phi0, u0, storage=storage)
+        if tile:
+            s.set_tile(*tile)
+        s.set_zchunk(zc).step(25)
+        h, g, u = [t.cpu().numpy() for t in s.export_state()]
+        assert np.array_equal(h, h0) and np.array_equal(g, g0) and np.array_equal(u, u_0), (zc, tile)
