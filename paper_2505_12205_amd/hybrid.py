@@ -61,21 +61,30 @@ def intact_length(phi_coarse):
 
 
 class HybridRollout:
-    """Network rollout of `doms` (list of (cfg, phi0, u0)) with solver fallback."""
+    """Network rollout of `doms` (list of (cfg, phi0, u0)) with solver
+    fallback, from the solver's state at lag `start` (0: the initial fields);
+    predictions whose budget violation exceeds `threshold` fall back."""
 
-    def __init__(self, net: SG.Network, doms, storage="fp16"):
+    def __init__(self, net: SG.Network, doms, storage="fp16", start=0, threshold=SG.FALLBACK_THRESHOLD):
         self.net, self.cfgs = net, [c for c, _, _ in doms]
         self.n = len(doms)
+        self.threshold = threshold
         assert self.n == net.batch
         c0 = self.cfgs[0]
         self.shape = (5, WINDOW, c0["ny"] // 2, c0["nx"] // 2)
         self.solver = [lbm.Batch([d], storage=storage) for d in doms]
-        self.sync = np.zeros(self.n, dtype=np.int64)  # lag of each solver state
+        self.sync = np.full(self.n, start, dtype=np.int64)  # lag of each solver state
         self.x = torch.empty((self.n,) + self.shape, device="cuda")
         for d, (c, phi0, u0) in enumerate(doms):
-            initial_coarse(c, phi0, u0, self.x[d])
+            if start == 0:
+                initial_coarse(c, phi0, u0, self.x[d])
+            else:
+                self.solver[d].step(start * LAG)
+                phi, u, p = self.solver[d].fields(0)
+                coarse_fields(phi, u, p, c, self.x[d])
         self.x_prev = self.x.clone()
-        self.lag = 0
+        self.lag = start
+        self.start = start
         self.fallbacks = []              # (lag, domain)
         self.t_net = self.t_solver = 0.0
 
@@ -96,7 +105,8 @@ class HybridRollout:
         pred = self.net.predict(self.x)
         torch.cuda.synchronize()
         self.t_net += time.perf_counter() - t0
-        bad = np.nonzero(SG.fallback_mask(self.x_prev, self.x, pred))[0] if self.lag > 0 else []
+        bad = (np.nonzero(SG.fallback_mask(self.x_prev, self.x, pred, self.threshold))[0]
+               if self.lag > self.start else [])
         self.lag += 1
         for d in bad:
             self._solver_state(int(d), pred[int(d)])
