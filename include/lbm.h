@@ -177,7 +177,8 @@ int lbm_set_store_hint(lbm_sim* s, int nontemporal);
 
 /* Resident blocks per compute unit of the persistent launches (1..64): the
  * interior kernels run as about CUs x blocks_per_cu blocks, each walking a
- * contiguous chunk of tiles. */
+ * contiguous chunk of tiles.  0: one block per tile (per z-chunk task of the
+ * marching kernel), refilled by the hardware dispatcher. */
 int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu);
 
 /* Autotuner: times trial_steps eager steps for each candidate tile shape,
@@ -249,7 +250,8 @@ int lbm_batch_export_state(lbm_batch* b, int dom, float* h_dev, float* g_dev, fl
  * `threshold` (the layer count if none).  Synchronises. */
 int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length);
 /* launch shape: threads per block bx*by (as lbm_set_tile), resident blocks
- * per compute unit of the persistent launches, non-temporal stores */
+ * per compute unit of the persistent launches (0: one block per tile, as
+ * lbm_set_blocks_per_cu), non-temporal stores */
 int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal);
 /* autotuner over tile shape x blocks per CU x store hint; cached per batch
  * shape for the process; advances the state by the trials; synchronises */

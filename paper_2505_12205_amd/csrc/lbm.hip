@@ -391,11 +391,12 @@ int build_launch(LaunchSet& ls, lbm_sim* const* v, int n, int bx, int by, int bp
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   // persistent launch: about bpc resident blocks per compute unit, each
-  // walking a contiguous chunk of tiles
-  const int want = std::max(1, std::min(std::max(tb, 1), cus * bpc));
+  // walking a contiguous chunk of tiles; bpc = 0: one block per tile (the
+  // dispatcher refills the compute units as blocks end)
+  const int want = bpc > 0 ? std::max(1, std::min(std::max(tb, 1), cus * bpc)) : std::max(tb, 1);
   ls.chunk = std::max(1, (tb + want - 1) / want);
   ls.grid = std::max(1, (tb + ls.chunk - 1) / ls.chunk);
-  const int mwant = std::max(1, std::min(std::max(kb, 1), cus * bpc));
+  const int mwant = bpc > 0 ? std::max(1, std::min(std::max(kb, 1), cus * bpc)) : std::max(kb, 1);
   ls.mchunk = std::max(1, (kb + mwant - 1) / mwant);
   ls.mgrid = std::max(1, (kb + ls.mchunk - 1) / ls.mchunk);
   return LBM_OK;
@@ -744,7 +745,7 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune_cache;
 
 const int kTiles[][2] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}, {64, 8}, {128, 4}, {32, 4}, {16, 16}};
-const int kBpc[] = {2, 4, 8};
+const int kBpc[] = {0, 2, 4, 8};
 // planes per z-marching task tried by the autotuners (D3Q19; 0 = tiled kernel)
 const int kZc[] = {0, 32};
 
@@ -914,7 +915,7 @@ int lbm_set_store_hint(lbm_sim* s, int nontemporal) {
 }
 
 int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu) {
-  if (!s || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad argument");
+  if (!s || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad argument");
   return set_launch(s, s->ls.bx, s->ls.by, blocks_per_cu, s->ls.nt, true);
 }
 
@@ -1215,7 +1216,7 @@ int lbm_batch_intact_length(lbm_batch* b, float threshold, int* length) {
 
 int lbm_batch_set_launch(lbm_batch* b, int bx, int by, int blocks_per_cu, int nontemporal) {
   if (!b) return fail(LBM_EINVAL, "null handle");
-  if (!tile_ok(bx, by) || blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad launch shape");
+  if (!tile_ok(bx, by) || blocks_per_cu < 0 || blocks_per_cu > 64) return fail(LBM_EINVAL, "bad launch shape");
   return batch_set_launch(b, bx, by, blocks_per_cu, nontemporal ? 1 : 0, true);
 }
 
