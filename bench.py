@@ -271,7 +271,10 @@ def main():
     from paper_2505_12205_amd import workloads as W
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     copy_gbs = copy_probe()
-    print(f"[bench] device copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    from paper_2505_12205_amd import probe
+    ceil = probe.ceilings()
+    print(f"[bench] device copy {copy_gbs:.0f} GB/s (torch); hand-written probes {ceil} GB/s",
+          file=sys.stderr, flush=True)
     if args.copy_probe_only:
         return
     if args.surrogate_only:
@@ -379,7 +382,9 @@ def main():
                      "kernel": ("kb_march" if zchunk_used else "kb_interior") +
                                " (fused macroscopic update + both collisions + AA streaming)",
                      "bytes_per_node": b_k, "kernel_ms": round(kt[1], 4),
-                     "phi_pass_ms": round(kt[0], 4), "device_copy_GBs": round(copy_gbs, 1)},
+                     "phi_pass_ms": round(kt[0], 4), "device_copy_GBs": round(copy_gbs, 1),
+                     "probe_GBs": ceil,
+                     "frac_of_inplace_probe": round(achieved / ceil["soa_inplace"], 4)},
         "step_bytes_per_node": b_step,
         "mass": mass,
         "kinetic": ke,

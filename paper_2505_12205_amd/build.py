@@ -1,7 +1,8 @@
 """Build the HIP C-ABI libraries for gfx950 with hipcc, in-tree:
 liblbm.so (the phase-field LBM step, include/lbm.h), libsurr.so (the
-learned surrogate's kernels, include/surrogate.h) and libdrops.so (the
-drop-size diagnostic, include/drops.h)."""
+learned surrogate's kernels, include/surrogate.h), libdrops.so (the
+drop-size diagnostic, include/drops.h) and libprobe.so (the HBM bandwidth
+probe of the measurements, include/probe.h)."""
 from __future__ import annotations
 
 import os
@@ -15,7 +16,8 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
 SURR_LIB = os.path.join(LIBDIR, "libsurr.so")
 DROPS_LIB = os.path.join(LIBDIR, "libdrops.so")
-TARGETS = [(LIB, ["lbm.hip"]), (SURR_LIB, ["nn.hip"]), (DROPS_LIB, ["ccl.hip"])]
+PROBE_LIB = os.path.join(LIBDIR, "libprobe.so")
+TARGETS = [(LIB, ["lbm.hip"]), (SURR_LIB, ["nn.hip"]), (DROPS_LIB, ["ccl.hip"]), (PROBE_LIB, ["probe.hip"])]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

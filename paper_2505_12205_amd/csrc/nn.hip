@@ -184,22 +184,6 @@ struct HaloTile {
   static constexpr int ELEMS = HZ * HY * HX * CI;
 };
 
-// LDS bank swizzle of the staged halo: the 16-byte chunk q of staged voxel
-// v sits at chunk q ^ ((v >> SH) & (CI / 8 - 1)), so that the 16-byte reads
-// of consecutive voxels (one per lane of a 16-lane row) spread over
-// distinct bank groups instead of sharing half (CI = 16) or a quarter
-// (CI = 32) of them.
-#ifndef NN_HALO_SWZ
-#define NN_HALO_SWZ 1
-#endif
-template <int CI>
-__device__ __forceinline__ int halo_at(int vox, int c) {
-  constexpr int P = CI / 8;
-  constexpr int SH = (P == 2 ? 2 : (P == 4 ? 1 : 0)) + (NN_HALO_SWZ == 2 ? 1 : 0);
-  if (NN_HALO_SWZ == 0) return vox * CI + c;
-  return vox * CI + ((((c >> 3) ^ (vox >> SH)) & (P - 1)) << 3);
-}
-
 struct HGeo {
   int n, d, h, w;          // input extent
   int od, oh, ow;          // output extent (U x input)
@@ -232,7 +216,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     v8bf val = {};
     if (gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
       val = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * CI + c8);
-    *(v8bf*)&halo[halo_at<CI>(vox, c8)] = val;
+    *(v8bf*)&halo[vox * CI + c8] = val;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -257,7 +241,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
       const int lz = U == 1 ? rz + kz : ((rz + kz - 1) >> 1) + 1;
       const int ly = U == 1 ? ry + ky : ((ry + ky - 1) >> 1) + 1;
       const int lx = U == 1 ? col + kx : ((col + kx - 1) >> 1) + 1;
-      a[m] = kin ? *(const v8bf*)&halo[halo_at<CI>((lz * HY + ly) * HX + lx, c)] : (v8bf){};
+      a[m] = kin ? *(const v8bf*)&halo[((lz * HY + ly) * HX + lx) * CI + c] : (v8bf){};
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : (v8bf){};

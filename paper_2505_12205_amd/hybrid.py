@@ -15,13 +15,15 @@ intact length over a window of lags (median above two nozzle diameters:
 jetting), two ways:
   - solver only: bisection, each probe one solver run of one domain through
     the window;
-  - surrogate-guided: the network rolls every domain out from its initial
-    fields and proposes the first jetting index; the solver then probes the
-    two domains around it, and bisection continues inside whatever bracket
-    those probes leave.
+  - surrogate-accelerated (AcceleratedSearch): each probe runs the solver to
+    a lag before the window and the network through it; the adjacent pair
+    the search ends on is confirmed by the solver from the kept states, and
+    the search repeats with any regime the confirmation corrects.
 Both searches end on the same adjacent pair of Weber numbers whenever the
-solver's regime is monotone in We, since every regime that decides the final
-bracket is a solver call.
+solver's regime is monotone in We, since the regimes of the final pair are
+solver calls.  (Network rollouts from the initial fields call every domain
+of the sweep jetting: the error of 250 chained predictions is too large for
+the intact length.)
 """
 from __future__ import annotations
 
@@ -36,6 +38,9 @@ from . import workloads as W
 
 LAG = 32
 WINDOW = 192
+# lag at which the accelerated search hands a probe from the solver to the
+# network: 16 lags before the regime window of lags 250..299
+START = 234
 
 
 def coarse_fields(phi, u, p, cfg, out):
@@ -83,6 +88,7 @@ class HybridRollout:
                 phi, u, p = self.solver[d].fields(0)
                 coarse_fields(phi, u, p, c, self.x[d])
         self.x_prev = self.x.clone()
+        self.solver_start = self.x.clone()
         self.lag = start
         self.start = start
         self.fallbacks = []              # (lag, domain)
@@ -122,38 +128,101 @@ def solver_regime(cfg, phi0, u0, window, storage="fp16"):
     t0 = time.perf_counter()
     b = lbm.Batch([(cfg, phi0, u0)], storage=storage)
     b.step(window[0] * LAG)
+    jet, med = _solver_window(b, cfg, window)
+    return jet, med, time.perf_counter() - t0
+
+
+def _solver_window(b, cfg, window):
+    """Regime from a one-domain solver batch standing at lag window[0]."""
     lb = []
-    for _ in range(window[0], window[1] + 1):
+    for k in range(window[0], window[1] + 1):
         lb.append(b.intact_length(0.5)[0])
-        b.step(LAG)
+        if k < window[1]:
+            b.step(LAG)
     torch.cuda.synchronize()
     med = float(np.median(lb)) / (2.0 * cfg["inlet_radius"])
-    return med > 2.0, med, time.perf_counter() - t0
+    return med > 2.0, med
 
 
-def network_regimes(net: SG.Network, doms, window):
-    """Regimes of all domains from network rollouts started at their initial
-    fields (batches of net.batch domains); returns (jetting[n], median L_b / D, seconds)."""
-    t0 = time.perf_counter()
-    n, bs = len(doms), net.batch
-    c0 = doms[0][0]
-    shape = (5, WINDOW, c0["ny"] // 2, c0["nx"] // 2)
-    med = np.zeros(n)
-    x = torch.empty((bs,) + shape, device="cuda")
-    for s in range(0, n, bs):
-        idx = list(range(s, min(s + bs, n)))
-        pad = idx + [idx[-1]] * (bs - len(idx))
-        for j, d in enumerate(pad):
-            c, phi0, u0 = doms[d]
-            initial_coarse(c, phi0, u0, x[j])
+class AcceleratedSearch:
+    """Bisection for the first jetting index in which each probe runs the
+    solver only to lag `start` and the network (batch 1) from there through
+    the window; the probed domain's solver state at lag `start` is kept.
+    The adjacent pair the search ends on is then confirmed by the solver,
+    continuing the kept states through the window.  A confirmed regime
+    overrides the network's call, and the search repeats with it until the
+    confirmed pair drips / jets, so the result is the solver-only one
+    whenever the solver's regime is monotone in We.  Solver steps are
+    counted: start * LAG per probe, (window[1] - start) * LAG per
+    confirmation."""
+
+    def __init__(self, net: SG.Network, doms, window, start, storage="fp16"):
+        assert net.batch == 1 and start <= window[0]
+        self.net, self.doms, self.window, self.start, self.storage = net, doms, window, start, storage
+        self.netcall, self.confirmed, self.state = {}, {}, {}
+        self.medians = {}
+        self.solver_steps = 0
+        self.probes, self.confirmations = [], []
+
+    def _network(self, i):
+        cfg, phi0, u0 = self.doms[i]
+        b = lbm.Batch([(cfg, phi0, u0)], storage=self.storage)
+        b.step(self.start * LAG)
+        self.solver_steps += self.start * LAG
+        x = torch.empty((1, 5, WINDOW, cfg["ny"] // 2, cfg["nx"] // 2), device="cuda")
+        coarse_fields(*b.fields(0), cfg, x[0])
         lb = []
-        for k in range(1, window[1] + 1):
-            x = net.predict(x)
-            if k >= window[0]:
-                lb.append(intact_length(x[:len(idx), 0].cpu().numpy()))
-        med[idx] = np.median(np.stack(lb), axis=0) / (2.0 * c0["inlet_radius"])
-    torch.cuda.synchronize()
-    return med > 2.0, med, time.perf_counter() - t0
+        for k in range(self.start + 1, self.window[1] + 1):
+            x = self.net.predict(x)
+            if k >= self.window[0]:
+                lb.append(intact_length(x[:, 0].cpu().numpy())[0])
+        med = float(np.median(lb)) / (2.0 * cfg["inlet_radius"])
+        self.state[i] = b
+        self.probes.append(i)
+        self.medians[("net", i)] = med
+        return med > 2.0
+
+    def call(self, i):
+        if i in self.confirmed:
+            return self.confirmed[i]
+        if i not in self.netcall:
+            self.netcall[i] = self._network(i)
+        return self.netcall[i]
+
+    def confirm(self, i):
+        if i not in self.confirmed:
+            self.call(i)  # the kept state comes from the probe
+            b = self.state.pop(i)
+            b.step((self.window[0] - self.start) * LAG)
+            jet, med = _solver_window(b, self.doms[i][0], self.window)
+            self.solver_steps += (self.window[1] - self.start) * LAG
+            self.confirmed[i] = jet
+            self.medians[("solver", i)] = med
+            self.confirmations.append(i)
+            del b
+        return self.confirmed[i]
+
+    def run(self):
+        """First jetting index (None if the last domain drips)."""
+        n = len(self.doms)
+        while True:
+            lo, hi = 0, n - 1
+            if not self.call(hi):
+                if not self.confirm(hi):
+                    return None
+                continue
+            if self.call(lo):
+                if self.confirm(lo):
+                    return lo
+                continue
+            while hi - lo > 1:
+                mid = (lo + hi) // 2
+                if self.call(mid):
+                    hi = mid
+                else:
+                    lo = mid
+            if not self.confirm(lo) and self.confirm(hi):
+                return hi
 
 
 def bisect(probe, lo, hi, known=None):
@@ -180,23 +249,6 @@ def bisect(probe, lo, hi, known=None):
         else:
             lo = mid
     return hi, calls
-
-
-def guided_bracket(probe, n, proposal):
-    """Surrogate-guided search: probe the proposed pair (proposal - 1,
-    proposal) first, then bisect inside the bracket the answers leave."""
-    known = {}
-    p = min(max(proposal, 1), n - 1)
-    known[p - 1] = probe(p - 1)
-    known[p] = probe(p)
-    calls = [p - 1, p]
-    if not known[p - 1] and known[p]:
-        return p, calls
-    if known[p - 1]:      # the transition lies at or below p - 1
-        first, more = bisect(probe, 0, p - 1, known)
-    else:                 # both drip: it lies above p
-        first, more = bisect(probe, p, n - 1, known)
-    return first, calls + more
 
 
 def weber_grid(n=64):

@@ -120,6 +120,24 @@ def test_drops_library_exports_every_declared_symbol_and_rejects_on_host():
     assert drops.lib.dr_components(1, 70, 5, 4, 3, 8, 1, 1, 1, 1, 1, C.byref(nc), 1, n, None) == drops.DR_EINVAL
 
 
+def test_probe_library_exports_every_declared_symbol_and_rejects_on_host():
+    from paper_2505_12205_amd import probe
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(pb_[a-z_0-9]+)\s*\(", txt)))
+    assert names == sorted(probe.EXPORTED)
+    for n in names:
+        assert hasattr(probe.lib, n), n
+    ms = C.c_double()
+    # arguments are checked before any device call
+    assert probe.lib.pb_stream(4, 1, 1, 1024, 0, 1, None, C.byref(ms)) == -1   # unknown kind
+    assert probe.lib.pb_stream(0, 1, 1, 1022, 0, 1, None, C.byref(ms)) == -1   # n not a multiple of 4
+    assert probe.lib.pb_stream(0, 1, None, 1024, 0, 1, None, C.byref(ms)) == -1  # copy without dst
+    assert probe.lib.pb_stream(3, 1, None, 19 * 64, 7, 1, None, C.byref(ms)) == -1  # q not 19 or 38
+    assert probe.lib.pb_stream(3, 1, None, 1024, 38, 1, None, C.byref(ms)) == -1  # 38 does not divide 1024
+    assert probe.lib.pb_stream(0, 1, 1, 1024, 0, 0, None, C.byref(ms)) == -1   # no passes
+    assert b"bad argument" in probe.lib.pb_last_error() or b"q must" in probe.lib.pb_last_error()
+
+
 def test_batch_layout_and_validation_on_host():
     """lbm_batch_state_bytes: the sum of the domains' 256-byte aligned
     layouts; batches of mixed lattice or storage, and empty ones, are

@@ -110,9 +110,11 @@ def test_batch_launch_shapes_agree():
     lbm = _lbm()
     doms = _small_sweep(seed=3)
     ref = lbm.Batch(doms).step(12)
-    alt = lbm.Batch(doms).set_launch(16, 16, 2, True).step(12)
-    for d in range(len(doms)):
-        assert (ref.export_state(d)[0] == alt.export_state(d)[0]).all()
+    for launch in ((16, 16, 2, True), (64, 4, 0, False)):
+        alt = lbm.Batch(doms).set_launch(*launch).step(12)
+        for d in range(len(doms)):
+            for a, r in zip(alt.export_state(d), ref.export_state(d)):
+                assert (a == r).all(), launch
 
 
 def test_batch_full_size_sweep_domains_equal_standalone():

@@ -392,7 +392,8 @@ def test_z_marching_kernel_equals_tiled_kernel(which, storage):
     """The D3Q19 interior kernel marching along z with the phase field staged
     in LDS gives bit for bit the state of the tiled kernel that reads the
     stencil from global memory, for several chunk lengths and tiles (ragged
-    last chunk, partial tiles, wall lanes and inlet/outlet faces in the jet)."""
+    last chunk, partial tiles, wall lanes and inlet/outlet faces in the jet),
+    with persistent launches and with one block per tile or task."""
     lbm = _lbm()
     if which == "rt":
         cfg, phi0, u0 = _rt_copy(37, 29, 23, seed=5)
@@ -400,11 +401,13 @@ def test_z_marching_kernel_equals_tiled_kernel(which, storage):
         cfg, phi0, u0 = _jet_copy(nx=24, ny=20, nz=37, seed=3)
     ref = lbm.Sim(cfg, phi0, u0, storage=storage).set_zchunk(0).step(25)
     h0, g0, u_0 = [t.cpu().numpy() for t in ref.export_state()]
-    for zc, tile in ((16, None), (5, (32, 8)), (1, (64, 4)), (64, (16, 16))):
-        _log(f"[gpu] z-marching {which} {storage} zc={zc} tile={tile}")
+    for zc, tile, bpc in ((16, None, 4), (5, (32, 8), 4), (1, (64, 4), 0), (64, (16, 16), 2), (0, None, 0),
+                          (7, (32, 4), 0)):
+        _log(f"[gpu] z-marching {which} {storage} zc={zc} tile={tile} blocks/CU={bpc}")
         s = lbm.Sim(cfg, phi0, u0, storage=storage)
         if tile:
             s.set_tile(*tile)
+        s.set_blocks_per_cu(bpc)
         s.set_zchunk(zc).step(25)
         h, g, u = [t.cpu().numpy() for t in s.export_state()]
-        assert np.array_equal(h, h0) and np.array_equal(g, g0) and np.array_equal(u, u_0), (zc, tile)
+        assert np.array_equal(h, h0) and np.array_equal(g, g0) and np.array_equal(u, u_0), (zc, tile, bpc)

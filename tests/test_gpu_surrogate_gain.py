@@ -108,13 +108,14 @@ def test_surrogate_gain_on_heldout_weber():
 
 
 def test_hybrid_rollout_with_solver_fallback():
-    """The network advances four held-out jets from their initial fields for
-    64 lags; every prediction that violates the phase-field budget by more
-    than the threshold is replaced by the solver's own advance of that domain
-    (from its last synchronised state).  Reported: the fallback share, the
-    wall time of the hybrid run against the solver alone, and the coarse
-    fields' error against the solver at the last lag, with and without the
-    fallback."""
+    """The network advances four held-out jets for 65 lags from the solver's
+    state at lag 234 (the lead-in of the regime window); every prediction
+    that violates the phase-field budget by more than the threshold is
+    replaced by the solver's own advance of that domain (from its last
+    synchronised state).  Run at the production threshold and at a tenth of
+    it, so that the fallback path is exercised.  Reported: the fallback
+    shares, wall times against the solver alone, and the coarse fields'
+    error against the solver at the last lag, with and without fallback."""
     import torch
     if not torch.cuda.is_available():
         pytest.fail("a GPU test ran without a GPU")
@@ -122,30 +123,33 @@ def test_hybrid_rollout_with_solver_fallback():
     from paper_2505_12205_amd import lbm
     from paper_2505_12205_amd import surrogate as SG
 
-    lags = 64
+    start, lags = HY.START, 65
     L = W.sweep_lengths()
     We = W.sweep_weber()
     held = [d for d in range(64) if d % 4 == 3]
     pick = sorted(held, key=lambda d: L[d])[:4]
     doms = W.jet_sweep(lengths=[L[d] for d in pick], webers=[We[d] for d in pick])
     cfgs = [c for c, _, _ in doms]
-    _log(f"[gpu] hybrid rollout We={[round(float(We[d]), 3) for d in pick]}")
+    _log(f"[gpu] hybrid rollout We={[round(float(We[d]), 3) for d in pick]} from lag {start}")
     shape = (5, HY.WINDOW, cfgs[0]["ny"] // 2, cfgs[0]["nx"] // 2)
     net = SG.Network(len(doms), *shape[1:], u_jet=cfgs[0]["inlet_u"])
     net.load(WEIGHTS)
-    hy = HY.HybridRollout(net, doms)
-    plain = HY.HybridRollout(net, doms)
-    t0 = time.perf_counter()
+    runs = {}
+    for name, thr in (("production", SG.FALLBACK_THRESHOLD), ("tight", 0.1 * SG.FALLBACK_THRESHOLD)):
+        hy = HY.HybridRollout(net, doms, start=start, threshold=thr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(lags):
+            hy.advance()
+        torch.cuda.synchronize()
+        runs[name] = (hy, time.perf_counter() - t0)
+    # the network alone (no fallback) from the same start
+    x = runs["production"][0].solver_start.clone()
     for _ in range(lags):
-        hy.advance()
-    torch.cuda.synchronize()
-    t_hybrid = time.perf_counter() - t0
-    # the network alone (no fallback): the same rollout with the check switched off
-    for _ in range(lags):
-        plain.x_prev.copy_(plain.x)
-        plain.x.copy_(net.predict(plain.x))
-    # the solver alone over the same lags
+        x = net.predict(x)
+    # the solver alone
     ref = lbm.Batch(doms, storage="fp16")
+    ref.step(start * LAG)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ref.step(lags * LAG)
@@ -156,30 +160,39 @@ def test_hybrid_rollout_with_solver_fallback():
         phi, u, p = ref.fields(d)
         HY.coarse_fields(phi, u, p, c, xr[d])
     sc = torch.tensor(SG.norm_scales(cfgs[0]["inlet_u"])[1], device="cuda").view(1, 5, 1, 1, 1)
-    err_h = float((((hy.x - xr) * sc) ** 2).mean())
-    err_p = float((((plain.x - xr) * sc) ** 2).mean())
-    dphi_h = float((hy.x[:, 0] - xr[:, 0]).abs().max())
-    share = len(hy.fallbacks) / (len(doms) * (lags - 1))
-    _log(f"hybrid: {len(hy.fallbacks)} fallbacks of {len(doms) * (lags - 1)} predictions ({share:.1%}), "
-         f"network {hy.t_net:.2f} s + solver catch-up {hy.t_solver:.2f} s = {t_hybrid:.2f} s; "
-         f"solver alone {t_solver:.2f} s")
-    _log(f"coarse-field MSE at lag {lags}: hybrid {err_h:.3e}, network alone {err_p:.3e}; "
-         f"hybrid max|dphi| {dphi_h:.3f}")
-    # every flagged prediction was replaced by the solver state of that lag
-    for lag, d in hy.fallbacks:
-        assert hy.sync[d] >= lag
-    assert err_h <= err_p * 1.05 + 1e-12
-    assert np.isfinite(err_h)
+
+    def mse(a):
+        return float((((a - xr) * sc) ** 2).mean())
+
+    err_p = mse(x)
+    _log(f"solver alone over the {lags} lags: {t_solver:.2f} s; network alone: MSE {err_p:.3e}, "
+         f"max|dphi| {float((x[:, 0] - xr[:, 0]).abs().max()):.3f}")
+    total = len(doms) * (lags - 1)
+    for name, (hy, t_h) in runs.items():
+        _log(f"hybrid ({name}, threshold {hy.threshold:.0e}): {len(hy.fallbacks)} fallbacks of {total} "
+             f"predictions, network {hy.t_net:.2f} s + solver catch-up {hy.t_solver:.2f} s = {t_h:.2f} s; "
+             f"MSE {mse(hy.x):.3e}, max|dphi| {float((hy.x[:, 0] - xr[:, 0]).abs().max()):.3f}")
+        # every flagged prediction was replaced by the solver state of that lag
+        for lag, d in hy.fallbacks:
+            assert hy.sync[d] >= lag
+        assert np.isfinite(mse(hy.x))
+        # a fallback can only bring a domain back onto the solver's trajectory
+        assert mse(hy.x) <= err_p * 1.05 + 1e-12
+    assert len(runs["tight"][0].fallbacks) > 0
+    if not runs["production"][0].fallbacks:
+        assert runs["production"][1] < t_solver
 
 
-def test_guided_bracket_equals_bisection():
+def test_accelerated_bisection_equals_solver_bisection():
     """The critical Weber number on the sweep's 64-point Weber grid, regimes
     called from the intact length over lags 250..299 (steps 8,000-9,568, the
-    window of the training data): solver-only bisection against the
-    surrogate-guided search (network rollouts of all 64 domains from their
-    initial fields propose the first jetting index, the solver confirms
-    around it).  Both must end on the same adjacent pair; both wall times
-    are reported."""
+    window of the training data).  Solver-only bisection, each probe a solver
+    run through the window, against the surrogate-accelerated search
+    (hybrid.AcceleratedSearch: the solver to lag 234, the network through
+    the window, the final pair confirmed by the solver from the kept
+    states).  Both must end on the same adjacent pair; the solver steps and
+    the wall times of both are reported, and the accelerated search must
+    take fewer solver steps."""
     import torch
     if not torch.cuda.is_available():
         pytest.fail("a GPU test ran without a GPU")
@@ -191,25 +204,29 @@ def test_guided_bracket_equals_bisection():
     We = W.sweep_weber()
     n = len(doms)
     cfg0 = doms[0][0]
-    net = SG.Network(32, HY.WINDOW, cfg0["ny"] // 2, cfg0["nx"] // 2, u_jet=cfg0["inlet_u"])
-    net.load(WEIGHTS)
-    probes_s = []
+    calls = []
 
     def probe(i):
         jet, med, dt = HY.solver_regime(*doms[i], window)
-        probes_s.append(dt)
+        calls.append(i)
         _log(f"solver probe We={We[i]:.3f}: median L_b/D {med:.2f} -> {'jetting' if jet else 'dripping'} ({dt:.1f} s)")
         return jet
 
     t0 = time.perf_counter()
-    first_b, calls_b = HY.bisect(probe, 0, n - 1)
+    first_b, _ = HY.bisect(probe, 0, n - 1)
     t_bisect = time.perf_counter() - t0
+    steps_b = len(calls) * window[1] * LAG
+    net = SG.Network(1, HY.WINDOW, cfg0["ny"] // 2, cfg0["nx"] // 2, u_jet=cfg0["inlet_u"])
+    net.load(WEIGHTS)
     t0 = time.perf_counter()
-    jet_net, med_net, t_roll = HY.network_regimes(net, doms, window)
-    proposal = int(np.argmax(jet_net)) if jet_net.any() else n - 1
-    first_g, calls_g = HY.guided_bracket(probe, n, proposal)
-    t_guided = time.perf_counter() - t0
-    _log(f"bisection: first jetting We={We[first_b]:.3f} after {len(calls_b)} solver probes, {t_bisect:.1f} s")
-    _log(f"guided: network proposes We={We[proposal]:.3f} ({t_roll:.1f} s of rollouts), first jetting "
-         f"We={We[first_g]:.3f} after {len(calls_g)} solver probes, {t_guided:.1f} s")
-    assert first_b is not None and first_g == first_b
+    acc = HY.AcceleratedSearch(net, doms, window, HY.START)
+    first_a = acc.run()
+    torch.cuda.synchronize()
+    t_acc = time.perf_counter() - t0
+    _log(f"solver bisection: first jetting We={We[first_b]:.3f} after {len(calls)} probes, "
+         f"{steps_b} solver steps, {t_bisect:.1f} s")
+    _log(f"accelerated: first jetting We={We[first_a]:.3f} after {len(acc.probes)} probes "
+         f"(network calls {[(We[i].round(3), acc.netcall[i]) for i in acc.probes]}) and "
+         f"{len(acc.confirmations)} confirmations, {acc.solver_steps} solver steps, {t_acc:.1f} s")
+    assert first_b is not None and first_a == first_b
+    assert acc.solver_steps < steps_b
