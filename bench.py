@@ -30,19 +30,22 @@ def algorithmic_bytes_per_node(q: int, d: int, pop_bytes: int):
     return 2 * 2 * q * pop_bytes + 2 * d * 4 + 8, kstep, kphi
 
 
-def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True, zchunk=None):
+def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True, zchunk=None, bpc=None):
     import torch
 
     from paper_2505_12205_amd import lbm
     sim = lbm.Sim(cfg, phi0, u0, storage=storage)
     if zchunk is not None:
         sim.set_zchunk(zchunk)
+    if bpc is not None:
+        sim.set_blocks_per_cu(bpc)
     if tile:
         sim.set_tile(*tile)
     elif autotune:
         choice = sim.autotune(trial_steps=6)
         print(f"[bench] {storage} autotune -> tile {choice[0]}x{choice[1]} nontemporal={choice[2]} "
-              f"z-chunk {sim.zchunk} {choice[3]:.3f} ms/step", file=sys.stderr, flush=True)
+              f"z-chunk {sim.zchunk} blocks/CU {sim.blocks_per_cu} {choice[3]:.3f} ms/step",
+              file=sys.stderr, flush=True)
     sim.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -54,7 +57,7 @@ def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True, zch
     return sim, dt, kt, mass, ke
 
 
-def run_jet(steps, warmup, forms=("fp32", "fp16", "bf16"), autotune=True):
+def run_jet(steps, warmup, forms=("fp32", "fp16", "bf16"), autotune=True, tile=None, zchunk=None, bpc=None):
     """The precision-form jet at its stated size (192 x 192 x 768, inlet radius
     12, rho* = 800, We = 5, Re = 300, convective outflow) in each storage
     form: MLUPS of the whole step and the fused kernel's algorithmic GB/s."""
@@ -65,7 +68,7 @@ def run_jet(steps, warmup, forms=("fp32", "fp16", "bf16"), autotune=True):
     n = cfg["nx"] * cfg["ny"] * cfg["nz"]
     out = {"nodes": n}
     for st in forms:
-        sim, dt, kt, _, _ = run_gpu(cfg, phi0, u0, st, steps, warmup, None, autotune)
+        sim, dt, kt, _, _ = run_gpu(cfg, phi0, u0, st, steps, warmup, tile, autotune, zchunk, bpc)
         _, bk, _ = algorithmic_bytes_per_node(19, 3, 4 if st == "fp32" else 2)
         out[st] = {"MLUPS": round(n * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
                    "step_kernel_ms": round(kt[1], 4), "phi_pass_ms": round(kt[0], 4),
@@ -172,11 +175,12 @@ def run_drops(reps=20):
             "label_Gnodes_per_s": round(n / t_label / 1e9, 2)}
 
 
-def counted_traffic():
+def counted_traffic(zchunk):
     """HBM bytes per launch of the fused FP32 step from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
     of known size), or None when the kernel source has changed since the
-    counters were taken."""
+    counters were taken or the run used the other interior kernel (tiled
+    for z_chunk 0, z-marching otherwise) than the one counted."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -189,6 +193,8 @@ def counted_traffic():
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     if h.hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+        return None, None
+    if (zchunk > 0) != (rec.get("z_chunk", 0) > 0):
         return None, None
     return float(rec["traffic_bytes_per_launch"]), rec.get("summary")
 
@@ -249,13 +255,18 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training step")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the 2 GiB copy (counter calibration)")
-    ap.add_argument("--blocks-per-cu", type=int, default=8, help="batched launch with --tile")
+    ap.add_argument("--blocks-per-cu", type=int, default=None,
+                    help="blocks per CU of the persistent launches, 0: one block per tile (with --tile; "
+                         "the batched launch defaults to 8)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only time the surrogate's training step (for profiling it alone)")
     ap.add_argument("--drops-only", action="store_true",
                     help="only run the drop-size diagnostic (for profiling it alone)")
     ap.add_argument("--no-drops", action="store_true", help="skip the drop-size diagnostic")
     ap.add_argument("--no-jet", action="store_true", help="skip the 192x192x768 jet in each storage form")
+    ap.add_argument("--jet-only", action="store_true",
+                    help="only run the 192x192x768 jet in the storage forms of --forms plus fp32 "
+                         "(for profiling it alone)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only run the batched Weber sweep (for profiling it alone)")
     args = ap.parse_args()
@@ -283,8 +294,14 @@ def main():
     if args.drops_only:
         print(json.dumps({"drops": run_drops()}), flush=True)
         return
+    if args.jet_only:
+        forms = ["fp32"] + [f for f in args.forms.split(",") if f and f != "fp32"]
+        print(json.dumps({"jet_192x192x768": run_jet(args.steps, args.warmup, forms, not args.no_autotune, tile,
+                                                     args.zchunk, args.blocks_per_cu)}), flush=True)
+        return
     if args.batch_only:
-        launch = (tile[0], tile[1], args.blocks_per_cu, False) if tile else None
+        bpc = 8 if args.blocks_per_cu is None else args.blocks_per_cu
+        launch = (tile[0], tile[1], bpc, False) if tile else None
         nb, dtb, ktb, lb = run_batch(args.steps, args.warmup, "fp16", not args.no_autotune, launch)
         print(json.dumps({"batched_fp16_MLUPS": round(nb * args.steps / dtb / 1e6, 1), "nodes": nb,
                           "ms_per_step": round(dtb / args.steps * 1e3, 3), "phi_ms": round(ktb[0], 3),
@@ -296,7 +313,7 @@ def main():
     print(f"[bench] workload {cfg['name']} N={N} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     sim, dt, kt, mass, ke = run_gpu(cfg, phi0, u0, "fp32", args.steps, args.warmup, tile,
-                                    not args.no_autotune, args.zchunk)
+                                    not args.no_autotune, args.zchunk, args.blocks_per_cu)
     mlups = N * args.steps / dt / 1e6
     b_step, b_k, b_phi = algorithmic_bytes_per_node(19, 3, 4)
     achieved = b_k * N / (kt[1] * 1e-3) / 1e9
@@ -304,13 +321,14 @@ def main():
           file=sys.stderr, flush=True)
     tile_used = sim.tile
     zchunk_used = sim.zchunk
+    bpc_used = sim.blocks_per_cu
     del sim
     torch.cuda.empty_cache()
 
     forms = {}
     for st in [f for f in args.forms.split(",") if f]:
         s2, dt2, kt2, _, _ = run_gpu(cfg, phi0, u0, st, max(20, args.steps // 2), 5, tile,
-                                     not args.no_autotune)
+                                     not args.no_autotune, args.zchunk, args.blocks_per_cu)
         n2 = max(20, args.steps // 2)
         _, bk2, _ = algorithmic_bytes_per_node(19, 3, 2)
         forms[st] = {"MLUPS": round(N * n2 / dt2 / 1e6, 1),
@@ -323,7 +341,7 @@ def main():
     if not args.no_bgk:  # the selectable single-relaxation operator on the same workload
         n2 = max(20, args.steps // 2)
         s2, dt2, kt2, _, _ = run_gpu(dict(cfg, collision="bgk"), phi0, u0, "fp32", n2, 5, tile,
-                                     not args.no_autotune)
+                                     not args.no_autotune, args.zchunk, args.blocks_per_cu)
         forms["bgk_fp32"] = {"MLUPS": round(N * n2 / dt2 / 1e6, 1),
                              "step_kernel_ms": round(kt2[1], 4),
                              "step_kernel_GBs": round(b_k * N / (kt2[1] * 1e-3) / 1e9, 1)}
@@ -358,7 +376,7 @@ def main():
         print(f"[bench] surrogate {forms['surrogate_bf16_mfma']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
-    traffic, traffic_src = counted_traffic()
+    traffic, traffic_src = counted_traffic(zchunk_used)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -374,7 +392,7 @@ def main():
         "data": "synthetic (analytic cosine-perturbed interface, seeded parameters)",
         "config": {"workload": "rayleigh_taylor_3d_d3q19", "nx": 256, "ny": 1024, "nz": 256,
                    "storage": "fp32", "atwood": 0.5, "reynolds": 3000, "W": 5,
-                   "tile": list(tile_used), "z_chunk": zchunk_used},
+                   "tile": list(tile_used), "z_chunk": zchunk_used, "blocks_per_cu": bpc_used},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_source": traffic_src,

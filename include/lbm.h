@@ -180,6 +180,7 @@ int lbm_set_store_hint(lbm_sim* s, int nontemporal);
  * contiguous chunk of tiles.  0: one block per tile (per z-chunk task of the
  * marching kernel), refilled by the hardware dispatcher. */
 int lbm_set_blocks_per_cu(lbm_sim* s, int blocks_per_cu);
+int lbm_get_blocks_per_cu(const lbm_sim* s, int* blocks_per_cu);
 
 /* Autotuner: times trial_steps eager steps for each candidate tile shape,
  * blocks per compute unit, store hint and (D3Q19) z-marching chunk (0 or 32

@@ -935,6 +935,12 @@ int lbm_get_zchunk(const lbm_sim* s, int* planes) {
   return LBM_OK;
 }
 
+int lbm_get_blocks_per_cu(const lbm_sim* s, int* blocks_per_cu) {
+  if (!s || !blocks_per_cu) return fail(LBM_EINVAL, "null argument");
+  *blocks_per_cu = s->ls.bpc;
+  return LBM_OK;
+}
+
 int lbm_get_tile(const lbm_sim* s, int* bx, int* by) {
   if (!s || !bx || !by) return fail(LBM_EINVAL, "null argument");
   *bx = s->ls.bx;

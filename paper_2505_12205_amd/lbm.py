@@ -69,6 +69,7 @@ def _load():
     L.lbm_set_store_hint.argtypes = [vp, C.c_int]
     L.lbm_set_zchunk.argtypes = [vp, C.c_int]
     L.lbm_get_zchunk.argtypes = [vp, C.POINTER(C.c_int)]
+    L.lbm_get_blocks_per_cu.argtypes = [vp, C.POINTER(C.c_int)]
     L.lbm_batch_set_zchunk.argtypes = [vp, C.c_int]
     L.lbm_set_blocks_per_cu.argtypes = [vp, C.c_int]
     L.lbm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -98,7 +99,7 @@ lib = _load()
 
 EXPORTED = ("lbm_state_bytes", "lbm_init", "lbm_step", "lbm_steps_done", "lbm_fields", "lbm_reduce",
             "lbm_export_state", "lbm_import_state", "lbm_checkpoint_bytes", "lbm_save", "lbm_load",
-            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_zchunk", "lbm_get_zchunk", "lbm_batch_set_zchunk", "lbm_set_blocks_per_cu", "lbm_autotune",
+            "lbm_set_tile", "lbm_get_tile", "lbm_set_store_hint", "lbm_set_zchunk", "lbm_get_zchunk", "lbm_batch_set_zchunk", "lbm_set_blocks_per_cu", "lbm_get_blocks_per_cu", "lbm_autotune",
             "lbm_kernel_times", "lbm_destroy", "lbm_last_error", "lbm_version",
             "lbm_batch_state_bytes", "lbm_batch_init", "lbm_batch_step", "lbm_batch_steps_done",
             "lbm_batch_reduce", "lbm_batch_reduce_noalloc", "lbm_batch_fields", "lbm_batch_export_state", "lbm_batch_intact_length",
@@ -267,6 +268,13 @@ class Sim:
     def zchunk(self) -> int:
         v = C.c_int()
         _check(lib.lbm_get_zchunk(self._h, C.byref(v)))
+        return v.value
+
+    @property
+    def blocks_per_cu(self) -> int:
+        """Blocks per CU of the persistent launches (0: one block per tile)."""
+        v = C.c_int()
+        _check(lib.lbm_get_blocks_per_cu(self._h, C.byref(v)))
         return v.value
 
     def set_blocks_per_cu(self, n: int):
