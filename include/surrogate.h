@@ -79,6 +79,24 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
 /* Flipped bf16 weight copy for the data gradient: wf[c][26 - k][o] = w[o][k][c]. */
 int sg_flip_weights(const uint16_t* w, int co, int ci, uint16_t* wf, void* stream);
 
+/* Folded bf16 weights of a x2 upsampling layer's data gradient, wu [ci][64][co]:
+ * wu[c][a][o] = sum over taps k with k_d in F(a_d) on every axis d of
+ * w[o][k][c], where a = (az * 4 + ay) * 4 + ax and F(a) = {2}, {1, 2}, {0, 1},
+ * {0} for a = 0..3 (summed in FP32, rounded once to bf16).  Along an axis,
+ * output p = 2 r - 1 + a of the layer reaches input voxel r through exactly
+ * the taps of F(a), over both upsampled copies of r. */
+int sg_fold_up_weights(const uint16_t* w, int co, int ci, uint16_t* wu, void* stream);
+
+/* Data gradient of a stride-1, x2 upsampling layer from the folded weights
+ * wu (sg_fold_up_weights): g[n, r, c] = sum over a in 4 x 4 x 4 and o of
+ * wu[c][a][o] dz[n, 2 r - 1 + a, o] (zero outside), a 4 x 4 x 4 stride-2
+ * gather with K = 64 co instead of 27 x 8 co.  Arguments and outputs (add,
+ * mask, da, dzp) as sg_conv3d_bwd_data with stride 1 and up 2; equal to it
+ * up to the rounding of the folded weights to bf16. */
+int sg_conv3d_bwd_data_up2(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wu, int co,
+                           const uint16_t* add, const uint16_t* mask, uint16_t* da, uint16_t* dzp,
+                           void* stream);
+
 /* Adam step with bias correction over a flat float buffer of `count`
  * parameters (master p, moments m and v, gradient g), step number t >= 1;
  * pb (nullable) receives the bf16 copy of the updated parameters. */

@@ -228,27 +228,66 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
   constexpr int K = 27 * CI;
   constexpr int csh = CI == 16 ? 4 : (CI == 32 ? 5 : 6);
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const int k = k0 + 8 * quad;  // K is a multiple of 32 for CI >= 32, and of 16 for CI = 16
-    const bool kin = k < K;
-    const int tap = kin ? (k >> csh) : 0, c = k - (tap << csh);
-    const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
-    v8bf a[MS], bb[NS];
+  if constexpr (U == 1) {
+    // A wave's MS rows are MS consecutive y rows of one z plane, so the
+    // staged voxel of row m and tap (kz, ky, kx) is that of row 0 plus
+    // m * HX (a compile-time stride: an immediate LDS offset) plus the tap's
+    // offset, which depends only on the K chunk and the lane's quad.  The
+    // tap offsets of the chunk are wave-uniform; the lane picks one of two.
+    static_assert(TY % MS == 0, "a wave's rows lie in one z plane");
+    const int r0 = wv * MS;
+    const int abase = (((r0 / TY) * HY + r0 % TY) * HX + col) * CI;
+    const uint16_t* wrow[NS];
 #pragma unroll
-    for (int m = 0; m < MS; ++m) {
-      const int r = wv * MS + m, rz = r / TY, ry = r % TY;
-      // staged voxel of virtual offset t = row/col + tap - 1: t + 1 (U = 1), floor(t / 2) + 1 (U = 2)
-      const int lz = U == 1 ? rz + kz : ((rz + kz - 1) >> 1) + 1;
-      const int ly = U == 1 ? ry + ky : ((ry + ky - 1) >> 1) + 1;
-      const int lx = U == 1 ? col + kx : ((col + kx - 1) >> 1) + 1;
-      a[m] = kin ? *(const v8bf*)&halo[((lz * HY + ly) * HX + lx) * CI + c] : (v8bf){};
+    for (int s = 0; s < NS; ++s) wrow[s] = wgt + (long long)(s * 16 + col) * K;
+    auto tap_off = [](int t) { return (((t / 9) * HY + (t / 3) % 3) * HX + t % 3) * CI; };
+    auto chunk = [&](int k0, bool tail) {
+      const int k = k0 + 8 * quad;
+      const bool kin = !tail || k < K;
+      const int t0 = k0 >> csh;  // tap of quad 0 (uniform)
+      const int o0 = tap_off(t0), o1 = tap_off(t0 + 1);
+      const int c = kin ? k - (t0 << csh) : 0;  // < 2 CI: past CI the lane's tap is t0 + 1
+      const int toff = (CI == 16 && c >= CI) ? o1 + (c - CI) : o0 + c;
+      v8bf a[MS], bb[NS];
+#pragma unroll
+      for (int m = 0; m < MS; ++m)
+        a[m] = kin ? *(const v8bf*)&halo[abase + toff + m * HX * CI] : (v8bf){};
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wrow[s] + k) : (v8bf){};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
+    };
+    constexpr int KF = K / 32 * 32;  // full chunks; CI = 16 leaves a half chunk
+#pragma unroll
+    for (int k0 = 0; k0 < KF; k0 += 32) chunk(k0, false);
+    if constexpr (KF < K) chunk(KF, true);
+  } else {
+    // x2 upsampling: the staged voxel of virtual offset t = row/col + tap - 1
+    // is floor(t / 2) + 1 along each axis.  (A separable, fully unrolled form
+    // of these addresses cut the VALU count but ran the 32 -> 16 layer 24 %
+    // slower: this loop's time is in the staging and the epilogue.)
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int k = k0 + 8 * quad;  // K is a multiple of 32 for CI >= 32
+      const int tap = k >> csh, c = k - (tap << csh);
+      const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+      v8bf a[MS], bb[NS];
+#pragma unroll
+      for (int m = 0; m < MS; ++m) {
+        const int r = wv * MS + m, rz = r / TY, ry = r % TY;
+        const int lz = ((rz + kz - 1) >> 1) + 1;
+        const int ly = ((ry + ky - 1) >> 1) + 1;
+        const int lx = ((col + kx - 1) >> 1) + 1;
+        a[m] = *(const v8bf*)&halo[((lz * HY + ly) * HX + lx) * CI + c];
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) bb[s] = ld8(wgt + (long long)(s * 16 + col) * K + k);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : (v8bf){};
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
   }
   // lane holds D[4 quad + r][col]: voxel x0 + 4 quad + r of row m, channel s*16 + col
 #pragma unroll
@@ -343,6 +382,86 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
   for (int k0 = 0; k0 < K; k0 += 32) {
     v8bf a[MS], b[NS];
     load(k0, a, b);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+  }
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long v = vbase + m * 16 + 4 * quad + r;
+      if (v >= g.mi) continue;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int c = s * 16 + col;
+        const long long i = v * CI + c;
+        float val = acc[m][s][r];
+        if (add) val += bf2f(add[i]);
+        if (da) da[i] = f2bf(val);
+        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
+        dzp[i] = f2bf(val);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// data gradient of a x2 upsampling layer with folded weights
+// ---------------------------------------------------------------------------
+// Along each axis the upsampled position 2 r + j (j = 0, 1) of input voxel r
+// is read by output p = 2 r + j + 1 - k, so over j and the taps k the
+// outputs p = 2 r - 1 + a (a = 0..3) reach r, each through the taps of the
+// fold set F(a) = [max(0, 2 - a), min(2, 3 - a)] ({2}, {1, 2}, {0, 1}, {0}).
+// With wu[c][a][o] = sum over k in F(az) x F(ay) x F(ax) of w[o][k][c]
+// (k_fold_up_w) the gradient is a 4 x 4 x 4 gather over dz with stride 2:
+// K = 64 co instead of the 27 x 8 co of the gather over taps and
+// sub-positions.
+template <int CI>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_up2(const uint16_t* __restrict__ dz,
+                                                           const uint16_t* __restrict__ wu, Geo g,
+                                                           const uint16_t* __restrict__ add,
+                                                           const uint16_t* __restrict__ mask,
+                                                           uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
+  constexpr int NS = CI / 16;
+  constexpr int MS = 8 / NS;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, quad = lane >> 4;
+  const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
+  int pz0[MS], py0[MS], px0[MS], nb[MS];
+  bool ok[MS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m) {
+    long long v = vbase + m * 16 + col;
+    ok[m] = v < g.mi;
+    if (!ok[m]) v = 0;
+    px0[m] = 2 * (int)(v % g.w) - 1;
+    v /= g.w;
+    py0[m] = 2 * (int)(v % g.h) - 1;
+    v /= g.h;
+    pz0[m] = 2 * (int)(v % g.d) - 1;
+    nb[m] = (int)(v / g.d);
+  }
+  v4f acc[MS][NS];
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const v8bf zero = {};
+  const int K = 64 * g.co, osh = ilog2(g.co);  // a multiple of 32: no partial chunk
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + 8 * quad;
+    const int t = k >> osh, o = k - (t << osh);
+    const int az = t >> 4, ay = (t >> 2) & 3, ax = t & 3;
+    v8bf a[MS], b[NS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+      const int pz = pz0[m] + az, py = py0[m] + ay, px = px0[m] + ax;
+      const bool v = ok[m] && pz >= 0 && py >= 0 && px >= 0 && pz < g.od && py < g.oh && px < g.ow;
+      a[m] = v ? ld8(dz + ((((long long)nb[m] * g.od + pz) * g.oh + py) * g.ow + px) * g.co + o) : zero;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) b[s] = ld8(wu + ((long long)(s * 16 + col) * 64 + t) * g.co + o);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -736,6 +855,21 @@ __global__ __launch_bounds__(256) void k_bwd_w_reduce(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
+// wu[c][a][o] (a = (az * 4 + ay) * 4 + ax) = sum over k in F(az) x F(ay) x F(ax)
+// of w[o][k][c], summed in FP32 in tap order and rounded once to bf16
+__global__ void k_fold_up_w(const uint16_t* __restrict__ w, int co, int ci, uint16_t* __restrict__ wu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [c][a][o]
+  if (i >= ci * 64 * co) return;
+  const int o = i % co, a = (i / co) % 64, c = i / (co * 64);
+  const int az = a >> 4, ay = (a >> 2) & 3, ax = a & 3;
+  float sum = 0.0f;
+  for (int kz = max(0, 2 - az); kz <= min(2, 3 - az); ++kz)
+    for (int ky = max(0, 2 - ay); ky <= min(2, 3 - ay); ++ky)
+      for (int kx = max(0, 2 - ax); kx <= min(2, 3 - ax); ++kx)
+        sum += bf2f(w[((long long)o * 27 + (kz * 3 + ky) * 3 + kx) * ci + c]);
+  wu[i] = f2bf(sum);
+}
+
 __global__ void k_flip_w(const uint16_t* __restrict__ w, int co, int ci, uint16_t* __restrict__ wf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over [o][k][c]
   if (i >= co * 27 * ci) return;
@@ -981,6 +1115,15 @@ void launch_bwd_data(const Geo& g, const uint16_t* dz, const uint16_t* wt, const
   const long long per_block = 4LL * 16 * MS;
   hipLaunchKernelGGL((k_conv_bwd_data<CI, S, U>), dim3(blocks_for(g.mi, (int)per_block)), dim3(256), 0, st, dz,
                      wt, g, add, mask, da, dzp);
+}
+
+template <int CI>
+void launch_bwd_data_up2(const Geo& g, const uint16_t* dz, const uint16_t* wu, const uint16_t* add,
+                         const uint16_t* mask, uint16_t* da, uint16_t* dzp, hipStream_t st) {
+  constexpr int MS = 8 / (CI / 16);
+  const long long per_block = 4LL * 16 * MS;
+  hipLaunchKernelGGL((k_conv_bwd_data_up2<CI>), dim3(blocks_for(g.mi, (int)per_block)), dim3(256), 0, st, dz, wu,
+                     g, add, mask, da, dzp);
 }
 
 template <int S, int U>
@@ -1405,6 +1548,27 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
   hipLaunchKernelGGL(k_bwd_w_reduce, dim3((nred + 63) / 64 + 1), dim3(256), 0, st, part, dbpart, nchunk, co, ci,
                      dw, db);
   return check_launch("sg_conv3d_bwd_weight");
+}
+
+int sg_fold_up_weights(const uint16_t* w, int co, int ci, uint16_t* wu, void* stream) {
+  if (!w || !wu || !chan_ok(co) || !chan_ok(ci)) return fail(SG_EINVAL, "bad weights");
+  const int n = ci * 64 * co;
+  hipLaunchKernelGGL(k_fold_up_w, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, w, co, ci, wu);
+  return check_launch("sg_fold_up_weights");
+}
+
+int sg_conv3d_bwd_data_up2(const uint16_t* dz, int n, int d, int h, int w, int ci, const uint16_t* wu, int co,
+                           const uint16_t* add, const uint16_t* mask, uint16_t* da, uint16_t* dzp,
+                           void* stream) {
+  int rc = check_conv(n, d, h, w, ci, co, 1, 2);
+  if (rc) return rc;
+  if (!dz || !wu || !dzp) return fail(SG_EINVAL, "null tensor");
+  const Geo g = make_geo(n, d, h, w, ci, co, 1, 2);
+  hipStream_t st = (hipStream_t)stream;
+  if (ci == 16) launch_bwd_data_up2<16>(g, dz, wu, add, mask, da, dzp, st);
+  else if (ci == 32) launch_bwd_data_up2<32>(g, dz, wu, add, mask, da, dzp, st);
+  else launch_bwd_data_up2<64>(g, dz, wu, add, mask, da, dzp, st);
+  return check_launch("sg_conv3d_bwd_data_up2");
 }
 
 int sg_flip_weights(const uint16_t* w, int co, int ci, uint16_t* wf, void* stream) {

@@ -37,6 +37,8 @@ def _load():
     L.sg_conv3d_bwd_weight_workspace.restype = sz
     L.sg_conv3d_bwd_weight.argtypes = [vp, i, i, i, i, i, vp, i, i, i, vp, sz, vp, vp, vp]
     L.sg_flip_weights.argtypes = [vp, i, i, vp, vp]
+    L.sg_fold_up_weights.argtypes = [vp, i, i, vp, vp]
+    L.sg_conv3d_bwd_data_up2.argtypes = [vp, i, i, i, i, i, vp, i, vp, vp, vp, vp, vp]
     L.sg_adam.argtypes = [vp, vp, vp, vp, ll, i, f, f, f, f, vp, vp]
     L.sg_normalize.argtypes = [vp, i, i, ll, vp, vp, vp, vp]
     L.sg_pack.argtypes = [vp, i, i, ll, i, vp, vp]
@@ -51,7 +53,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("sg_last_error", "sg_conv3d_fwd", "sg_conv3d_bwd_data", "sg_conv3d_bwd_weight_workspace",
-            "sg_conv3d_bwd_weight", "sg_flip_weights", "sg_adam", "sg_normalize", "sg_pack",
+            "sg_conv3d_bwd_weight", "sg_flip_weights", "sg_fold_up_weights", "sg_conv3d_bwd_data_up2", "sg_adam", "sg_normalize", "sg_pack",
             "sg_residual_loss", "sg_unpack", "sg_coarsen", "sg_phi_budget", "sg_gather")
 
 
@@ -92,6 +94,25 @@ def conv3d_bwd_data(dz, wf, n, d, h, w, ci, stride=1, up=1, add=None, mask=None,
     _check(lib.sg_conv3d_bwd_data(_p(dz), n, d, h, w, ci, _p(_bf(wf)), co, stride, up, _p(add), _p(mask), _p(da),
                                   _p(dzp), _s(stream)))
     return dzp
+
+
+def conv3d_bwd_data_up2(dz, wu, n, d, h, w, ci, add=None, mask=None, da=None, dzp=None, stream=None):
+    """Data gradient of a x2 upsampling layer: dz [n, 2d, 2h, 2w, co] bf16, wu [ci, 64, co]
+    bf16 (fold_up_weights) -> dzp [n, d, h, w, ci]."""
+    co = _bf(dz).shape[-1]
+    if dzp is None:
+        dzp = torch.empty((n, d, h, w, ci), dtype=torch.bfloat16, device=dz.device)
+    _check(lib.sg_conv3d_bwd_data_up2(_p(dz), n, d, h, w, ci, _p(_bf(wu)), co, _p(add), _p(mask), _p(da),
+                                      _p(dzp), _s(stream)))
+    return dzp
+
+
+def fold_up_weights(w, co, ci, wu=None, stream=None):
+    """wu[c][a][o] = sum of w[o][k][c] over the fold set of a (sg_fold_up_weights)."""
+    if wu is None:
+        wu = torch.empty((ci, 64, co), dtype=torch.bfloat16, device=w.device)
+    _check(lib.sg_fold_up_weights(_p(_bf(w)), co, ci, _p(wu), _s(stream)))
+    return wu
 
 
 def bwd_weight_workspace(n, d, h, w, ci, co, stride=1, up=1):

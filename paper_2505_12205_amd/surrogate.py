@@ -124,7 +124,10 @@ class Network:
         sources = {L["skip"] for L in self.lay.values() if L["skip"]}
         for (name, *_r) in self.spec:
             L = self.lay[name]
-            self.WF[name] = torch.empty((L["cip"], 27, L["cop"]), dtype=torch.bfloat16, device=self.dev)
+            if L["u"] == 2 and L["s"] == 1:  # folded weights of the x2 upsampling data gradient
+                self.WF[name] = torch.empty((L["cip"], 64, L["cop"]), dtype=torch.bfloat16, device=self.dev)
+            else:
+                self.WF[name] = torch.empty((L["cip"], 27, L["cop"]), dtype=torch.bfloat16, device=self.dev)
             self.y[name] = self._act(name)
             if L["skip"]:
                 self.yr[name] = self._act(name)
@@ -185,7 +188,10 @@ class Network:
     def _flip(self):
         for (name, *_r) in self.spec:
             L = self.lay[name]
-            nn.flip_weights(self._w(name), L["cop"], L["cip"], self.WF[name], stream=self.stream)
+            if L["u"] == 2 and L["s"] == 1:
+                nn.fold_up_weights(self._w(name), L["cop"], L["cip"], self.WF[name], stream=self.stream)
+            else:
+                nn.flip_weights(self._w(name), L["cop"], L["cip"], self.WF[name], stream=self.stream)
 
     def _w(self, name):
         L = self.lay[name]
@@ -235,10 +241,16 @@ class Network:
             mask = None
             if P["relu"]:
                 mask = self.yr[prev] if P["skip"] else self.y[prev]
-            nn.conv3d_bwd_data(self.dz[name], self.WF[name], self.batch, *self.ext_in[name], L["cip"],
-                               L["s"], L["u"], add=self.gskip.get(prev), mask=mask,
-                               da=self.gskip[P["skip"]] if P["skip"] else None, dzp=self.dz[prev],
-                               stream=self.stream)
+            if L["u"] == 2 and L["s"] == 1:
+                nn.conv3d_bwd_data_up2(self.dz[name], self.WF[name], self.batch, *self.ext_in[name], L["cip"],
+                                       add=self.gskip.get(prev), mask=mask,
+                                       da=self.gskip[P["skip"]] if P["skip"] else None, dzp=self.dz[prev],
+                                       stream=self.stream)
+            else:
+                nn.conv3d_bwd_data(self.dz[name], self.WF[name], self.batch, *self.ext_in[name], L["cip"],
+                                   L["s"], L["u"], add=self.gskip.get(prev), mask=mask,
+                                   da=self.gskip[P["skip"]] if P["skip"] else None, dzp=self.dz[prev],
+                                   stream=self.stream)
 
     def step(self):
         self.t += 1

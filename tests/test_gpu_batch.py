@@ -117,6 +117,28 @@ def test_batch_launch_shapes_agree():
                 assert (a == r).all(), launch
 
 
+def test_batch_fp16_sweep_domain_matches_oracle():
+    """The Weber sweep's real configuration (96 x 96 x L_k, FP16 deviation
+    storage, the sweep's mobility and walls): the two shortest domains run
+    batched for 200 steps, and the shorter one is compared with the FP64
+    oracle at every node (phase field within 1e-3)."""
+    lbm = _lbm()
+    L = W.sweep_lengths()
+    We = W.sweep_weber()
+    idx = [int(k) for k in np.argsort(L)[:2]]
+    doms = W.jet_sweep(lengths=[L[k] for k in idx], webers=[We[k] for k in idx])
+    _log(f"[gpu] fp16 sweep domains vs oracle {[(int(L[k]), round(float(We[k]), 3)) for k in idx]}")
+    b = lbm.Batch(doms, storage="fp16").step(200)
+    cfg, phi0, u0 = doms[0]
+    o = oracle.Oracle(cfg).init(phi0, u0).step(200)
+    phi_o, u_o, _ = o.fields()
+    phi_g, u_g, _ = b.fields(0)
+    ephi = np.abs(phi_g.cpu().numpy() - phi_o).max()
+    eu = np.abs(u_g.cpu().numpy() - u_o).max() / max(np.abs(u_o).max(), 1e-30)
+    _log(f"fp16 sweep domain 0 ({cfg['nx']}x{cfg['ny']}x{cfg['nz']}): max|dphi|={ephi:.3e} rel_u={eu:.3e}")
+    assert np.isfinite(eu) and ephi <= 1e-3
+
+
 def test_batch_full_size_sweep_domains_equal_standalone():
     """The two shortest domains of the Weber sweep (96 x 96 x L, FP16 storage)
     batched and standalone, 20 steps, bitwise."""

@@ -150,6 +150,20 @@ def test_conv_data_gradient(case):
     assert (np.abs(_ncdhw(dzp, ci) - g * (mask > 0)) <= tol).all()
     plain = nn.conv3d_bwd_data(_ndhwc(torch, dz, cop), WT, n, d, h, w, cip, s, u)
     assert (np.abs(_ncdhw(plain, ci) - dx) <= 2.0 ** -8 * np.abs(dx) + 1e-5 * dxa + 1e-6).all()
+    if s == 1 and u == 2:
+        # the folded form: the folded weights are rounded once more to bf16
+        # (half an ulp, 2^-9 of each, bounded by the gradient of |w| and |dz|)
+        WU = nn.fold_up_weights(W, cop, cip)
+        da2 = torch.empty_like(da)
+        dzp2 = nn.conv3d_bwd_data_up2(_ndhwc(torch, dz, cop), WU, n, d, h, w, cip, add=_ndhwc(torch, add, cip),
+                                      mask=_ndhwc(torch, mask, cip), da=da2)
+        tol2 = tol + 2.0 ** -9 * dxa
+        e2 = np.abs(_ncdhw(da2, ci) - g)
+        _log(f"conv data grad {case} (folded): max err {e2.max():.3e}")
+        assert (e2 <= tol2).all()
+        assert (np.abs(_ncdhw(dzp2, ci) - g * (mask > 0)) <= tol2).all()
+        plain2 = nn.conv3d_bwd_data_up2(_ndhwc(torch, dz, cop), WU, n, d, h, w, cip)
+        assert (np.abs(_ncdhw(plain2, ci) - dx) <= 2.0 ** -8 * np.abs(dx) + (1e-5 + 2.0 ** -9) * dxa + 1e-6).all()
 
 
 @pytest.mark.parametrize("case", CASES)
