@@ -23,7 +23,10 @@
  *   kind 4  as kind 3 on q arrays of 2 n / q 16-bit values, one value per
  *           lane (2-byte accesses, 8 n);
  *   kind 5  as kind 4 with two adjacent values per lane (4-byte accesses,
- *           8 n).
+ *           8 n);
+ *   kind 6  src viewed as q arrays of n / q floats, read; their sum per
+ *           element written to dst (n / q floats), 512-lane blocks: the
+ *           phase-field pass's pattern (4 n + 4 n / q).
  * Returns 0, or a negative code with pb_last_error() describing it (per
  * thread): -1 bad argument, -3 device error. */
 #pragma once

@@ -48,6 +48,18 @@ __global__ __launch_bounds__(512) void k_soa_t(T* __restrict__ f, size_t m) {
   for (int q = 0; q < Q; ++q) f[(Q - 1 - q) * m + i] = v[q];
 }
 
+// q arrays read, one float per lane each, their sum written to one array
+// (the phase-field pass's pattern: 19 reads, one write per node)
+template <int Q>
+__global__ __launch_bounds__(512) void k_soa_sum(const float* __restrict__ f, float* __restrict__ out, size_t m) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) s += f[q * m + i];
+  out[i] = s;
+}
+
 template <typename T>
 void launch_soa(int q, void* src, size_t m, hipStream_t st) {
   const unsigned gm = (unsigned)((m + 511) / 512);
@@ -70,8 +82,16 @@ void launch(int kind, void* src, void* dst, size_t n, int q, hipStream_t st) {
     launch_soa<float>(q, src, n / (size_t)q, st);
   else if (kind == 4)
     launch_soa<uint16_t>(q, src, 2 * n / (size_t)q, st);
-  else
+  else if (kind == 5)
     launch_soa<uint32_t>(q, src, n / (size_t)q, st);
+  else {
+    const size_t m = n / (size_t)q;
+    const unsigned gm = (unsigned)((m + 511) / 512);
+    if (q == 19)
+      hipLaunchKernelGGL(k_soa_sum<19>, dim3(gm), dim3(512), 0, st, (const float*)src, (float*)dst, m);
+    else
+      hipLaunchKernelGGL(k_soa_sum<38>, dim3(gm), dim3(512), 0, st, (const float*)src, (float*)dst, m);
+  }
 }
 
 }  // namespace
@@ -79,9 +99,9 @@ void launch(int kind, void* src, void* dst, size_t n, int q, hipStream_t st) {
 extern "C" {
 
 int pb_stream(int kind, void* src, void* dst, size_t n, int q, int reps, void* stream, double* ms_out) {
-  if (kind < 0 || kind > 5 || !src || !ms_out || reps < 1 || n == 0 || n % 4 || n >= ((size_t)1 << 33))
+  if (kind < 0 || kind > 6 || !src || !ms_out || reps < 1 || n == 0 || n % 4 || n >= ((size_t)1 << 33))
     return fail(-1, "pb_stream: bad argument");
-  if (kind <= 2 && !dst) return fail(-1, "pb_stream: dst is required for kinds 0-2");
+  if ((kind <= 2 || kind == 6) && !dst) return fail(-1, "pb_stream: dst is required for kinds 0-2 and 6");
   if (kind >= 3 && ((q != 19 && q != 38) || n % (size_t)q))
     return fail(-1, "pb_stream: q must be 19 or 38 and divide n");
   hipStream_t st = (hipStream_t)stream;

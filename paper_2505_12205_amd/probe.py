@@ -1,7 +1,8 @@
 """ctypes binding of libprobe.so (include/probe.h): hand-written streaming
 kernels that measure the practical HBM ceiling (copy, non-temporal copy,
-read, and the fused step's in-place access pattern over 38 arrays of FP32,
-or of 16-bit values at one or two per lane).
+read, the fused step's in-place access pattern over 38 arrays of FP32 or
+of 16-bit values at one or two per lane, and the phase-field pass's sum of
+19 arrays).
 
 Argument marshalling only; torch tensors provide device memory and the
 stream.  Importing this module loads the library and raises if it has not
@@ -32,9 +33,11 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pb_stream", "pb_last_error")
-KINDS = {"copy": 0, "copy_nt": 1, "read": 2, "soa_inplace": 3, "soa16_inplace": 4, "soa16x2_inplace": 5}
+KINDS = {"copy": 0, "copy_nt": 1, "read": 2, "soa_inplace": 3, "soa16_inplace": 4, "soa16x2_inplace": 5,
+         "soa_sum19": 6}
 # bytes moved per float of the buffer and pass
 BYTES_PER_FLOAT = {k: (4 if k == "read" else 8) for k in KINDS}
+BYTES_PER_FLOAT["soa_sum19"] = 4 + 4 / 19
 
 
 def stream_ms(kind: str, src: torch.Tensor, dst: torch.Tensor | None = None, q: int = 0, reps: int = 10) -> float:
@@ -51,14 +54,23 @@ def stream_ms(kind: str, src: torch.Tensor, dst: torch.Tensor | None = None, q: 
 def ceilings(gib: float = 2.0, soa_gib: float = 9.5, reps: int = 10) -> dict:
     """GB/s of each probe kernel: the copies and the read on buffers of
     `gib` GiB, the in-place passes over 38 arrays of soa_gib / 38 GiB in all
-    (9.5 GiB: the populations of the 256 x 1024 x 256 FP32 workload)."""
+    (9.5 GiB: the populations of the 256 x 1024 x 256 FP32 workload), the sum
+    of 19 arrays over half of that (the phase field's populations)."""
     out = {}
-    for kinds, size in ((("copy", "copy_nt", "read"), gib), (("soa_inplace", "soa16_inplace", "soa16x2_inplace"), soa_gib)):
-        n = int(size * (1 << 30) // 4) // 152 * 152  # a multiple of 4 and of 38
+    groups = ((("copy", "copy_nt", "read"), gib), (("soa_inplace", "soa16_inplace", "soa16x2_inplace"), soa_gib),
+              (("soa_sum19",), soa_gib / 2))
+    for kinds, size in groups:
+        n = int(size * (1 << 30) // 4) // 152 * 152  # a multiple of 4, of 19 and of 38
         a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a) if "copy" in kinds else None
+        if "copy" in kinds:
+            b = torch.empty_like(a)
+        elif "soa_sum19" in kinds:
+            b = torch.empty(n // 19, dtype=torch.float32, device="cuda")
+        else:
+            b = None
         for kind in kinds:
-            ms = stream_ms(kind, a, b, q=38 if kind.startswith("soa") else 0, reps=reps)
+            q = 19 if kind == "soa_sum19" else (38 if kind.startswith("soa") else 0)
+            ms = stream_ms(kind, a, b, q=q, reps=reps)
             out[kind] = round(BYTES_PER_FLOAT[kind] * n / (ms * 1e-3) / 1e9, 1)
         del a, b
         torch.cuda.empty_cache()

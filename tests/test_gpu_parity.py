@@ -386,17 +386,20 @@ def test_jet_config3_parity_copy_64x64x256():
         assert worst[st] <= tol[st], (st, worst[st])
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16"])
-@pytest.mark.parametrize("which", ["rt", "jet"])
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("which", ["rt", "jet", "rt-bgk"])
 def test_z_marching_kernel_equals_tiled_kernel(which, storage):
     """The D3Q19 interior kernel marching along z with the phase field staged
     in LDS gives bit for bit the state of the tiled kernel that reads the
     stencil from global memory, for several chunk lengths and tiles (ragged
     last chunk, partial tiles, wall lanes and inlet/outlet faces in the jet),
-    with persistent launches and with one block per tile or task."""
+    with persistent launches and with one block per tile or task, for the
+    WMRT and the BGK operator and every storage form."""
     lbm = _lbm()
-    if which == "rt":
+    if which.startswith("rt"):
         cfg, phi0, u0 = _rt_copy(37, 29, 23, seed=5)
+        if which == "rt-bgk":
+            cfg = dict(cfg, collision="bgk")
     else:
         cfg, phi0, u0 = _jet_copy(nx=24, ny=20, nz=37, seed=3)
     ref = lbm.Sim(cfg, phi0, u0, storage=storage).set_zchunk(0).step(25)
