@@ -55,6 +55,7 @@ __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c) {
 // gfx950's 16 x 16 x 32 form: every lane holds 8 consecutive K values of its
 // A row and of its B column (K index 8 (lane / 16) + j), D as above
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u __attribute__((ext_vector_type(8)));  // 8 bf16 bit patterns
 __device__ __forceinline__ v8bf ld8(const uint16_t* p) { return *(const v8bf*)p; }
 __device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -85,6 +86,54 @@ Geo make_geo(int n, int d, int h, int w, int ci, int co, int s, int u) {
 }
 
 // ---------------------------------------------------------------------------
+// epilogues: accumulators staged in LDS, written 16 bytes per lane
+// ---------------------------------------------------------------------------
+// A wave's accumulators (lane: D[4 quad + r][col] of row tile m and channel
+// tile s) are staged in LDS as FP32 [16 MS voxels][16 NS channels]; every
+// lane then takes 8 consecutive channels of one voxel, so the global
+// accesses (add, mask, da, dzp) are 16 bytes per lane.  vox(m, xl) is the
+// global voxel of the wave's voxel xl in row m, or -1 outside the grid.
+template <int MS, int NS>
+__device__ __forceinline__ void stage_acc(float* stage, const v4f (&acc)[MS][NS], int quad, int col) {
+  constexpr int CW = 16 * NS;
+#pragma unroll
+  for (int m = 0; m < MS; ++m)
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) stage[(m * 16 + 4 * quad + r) * CW + s * 16 + col] = acc[m][s][r];
+}
+
+template <int MS, int NS, class Vox>
+__device__ __forceinline__ void dgrad_epilogue(const float* stage, int lane, Vox vox,
+                                               const uint16_t* __restrict__ add,
+                                               const uint16_t* __restrict__ mask, uint16_t* __restrict__ da,
+                                               uint16_t* __restrict__ dzp) {
+  constexpr int CW = 16 * NS, G = CW / 8, VOX = 16 * MS;
+#pragma unroll
+  for (int j = 0; j < VOX * G / 64; ++j) {
+    const int f = j * 64 + lane, vl = f / G, c0 = (f % G) * 8;
+    const long long v = vox(vl / 16, vl % 16);
+    if (v < 0) continue;
+    const long long i = v * CW + c0;
+    const v4f lo = *(const v4f*)&stage[vl * CW + c0], hi = *(const v4f*)&stage[vl * CW + c0 + 4];
+    v8u av = {}, mv = {}, od, oz;
+    if (add) av = *(const v8u*)(add + i);
+    if (mask) mv = *(const v8u*)(mask + i);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float val = e < 4 ? lo[e] : hi[e - 4];
+      if (add) val += bf2f(av[e]);
+      od[e] = f2bf(val);
+      if (mask && !(bf2f(mv[e]) > 0.0f)) val = 0.0f;
+      oz[e] = f2bf(val);
+    }
+    if (da) *(v8u*)(da + i) = od;
+    *(v8u*)(dzp + i) = oz;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // forward: y[v, o] = act(b[o] + sum_{k,c} w[o,k,c] X[src(v,k), c]) (+ skip)
 // ---------------------------------------------------------------------------
 template <int CO, int S, int U>
@@ -94,6 +143,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
                                                   uint16_t* __restrict__ yr, Geo g, int relu) {
   constexpr int NS = CO / 16;
   constexpr int MS = 8 / NS;
+  __shared__ __attribute__((aligned(16))) float fw_stage[4 * 16 * MS * CO];  // the epilogue's staging
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
@@ -144,24 +194,32 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 #pragma unroll
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
   }
-  // lane holds D[4 quad + r][col]: voxel row 4 quad + r, channel col
+  // lane holds D[4 quad + r][col]: voxel row 4 quad + r, channel col; staged
+  // in LDS, then written 8 channels of one voxel per lane (16-byte accesses)
+  float* stage = fw_stage + wv * (16 * MS) * CO;
+  stage_acc<MS, NS>(stage, acc, quad, col);
+  __syncthreads();
+  constexpr int G = CO / 8;
 #pragma unroll
-  for (int m = 0; m < MS; ++m)
+  for (int j = 0; j < 16 * MS * G / 64; ++j) {
+    const int f = j * 64 + lane, vl = f / G, c0 = (f % G) * 8;
+    const long long v = vbase + vl;
+    if (v >= g.mo) continue;
+    const long long i = v * CO + c0;
+    const v4f lo = *(const v4f*)&stage[vl * CO + c0], hi = *(const v4f*)&stage[vl * CO + c0 + 4];
+    v8u sv = {}, orr, oy;
+    if (skip) sv = *(const v8u*)(skip + i);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long v = vbase + m * 16 + 4 * quad + r;
-      if (v >= g.mo) continue;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int o = s * 16 + col;
-        float val = acc[m][s][r] + bias[o];
-        if (relu) val = fmaxf(val, 0.0f);
-        const long long i = v * CO + o;
-        if (yr) yr[i] = f2bf(val);
-        if (skip) val += bf2f(skip[i]);
-        y[i] = f2bf(val);
-      }
+    for (int e = 0; e < 8; ++e) {
+      float val = (e < 4 ? lo[e] : hi[e - 4]) + bias[c0 + e];
+      if (relu) val = fmaxf(val, 0.0f);
+      orr[e] = f2bf(val);
+      if (skip) val += bf2f(sv[e]);
+      oy[e] = f2bf(val);
     }
+    if (yr) *(v8u*)(yr + i) = orr;
+    *(v8u*)(y + i) = oy;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -198,7 +256,10 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
                                                    uint16_t* __restrict__ y2, HGeo g, int relu) {
   using T = HaloTile<CI, CO, U>;
   constexpr int NS = T::NS, MS = T::MS, TY = T::TY, TZ = T::TZ, HX = T::HX, HY = T::HY, HZ = T::HZ;
-  __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS];
+  // the halo, then (after the K loop) the epilogue's FP32 staging of the
+  // four waves' accumulators: the larger of the two
+  constexpr int STAGE_ELEMS = 4 * 16 * MS * 16 * NS * 2;
+  __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS > STAGE_ELEMS ? T::ELEMS : STAGE_ELEMS];
   int b = blockIdx.x;
   const int tx = b % g.ntx;
   b /= g.ntx;
@@ -290,33 +351,49 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     }
   }
   // lane holds D[4 quad + r][col]: voxel x0 + 4 quad + r of row m, channel s*16 + col
+  constexpr int VOX = 16 * MS, CW = 16 * NS;  // a wave's voxels and channels
+  // Stage the accumulators through the halo's LDS (the halo is no longer
+  // read), then give every lane 8 consecutive channels of one voxel: the
+  // epilogue's global accesses become 16 bytes per lane, contiguous across
+  // lanes, instead of 2 bytes per lane in 32-byte pieces.
+  __syncthreads();
+  float* stage = (float*)halo + wv * VOX * CW;
 #pragma unroll
-  for (int m = 0; m < MS; ++m) {
-    const int rr = wv * MS + m, gz = z0 + rr / TY, gy = y0 + rr % TY;
-    if (gz >= g.od || gy >= g.oh) continue;
+  for (int m = 0; m < MS; ++m)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gx = x0 + 4 * quad + r;
-      if (gx >= g.ow) continue;
-      const long long v = (((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx;
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int o = s * 16 + col;
-        const long long i = v * CO + o;
-        float val = acc[m][s][r];
-        if (MODE == 0) {
-          val += bias[o];
-          if (relu) val = fmaxf(val, 0.0f);
-          if (y2) y2[i] = f2bf(val);
-          if (other) val += bf2f(other[i]);
-        } else {
-          if (other) val += bf2f(other[i]);
-          if (y2) y2[i] = f2bf(val);
-          if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
-        }
-        y[i] = f2bf(val);
+      for (int r = 0; r < 4; ++r) stage[(m * 16 + 4 * quad + r) * CW + s * 16 + col] = acc[m][s][r];
+  __syncthreads();
+  constexpr int G = CW / 8;  // 8-channel groups per voxel
+#pragma unroll
+  for (int j = 0; j < VOX * G / 64; ++j) {
+    const int f = j * 64 + lane, vl = f / G, c0 = (f % G) * 8;
+    const int m = vl / 16, xl = vl % 16;
+    const int rr = wv * MS + m, gz = z0 + rr / TY, gy = y0 + rr % TY, gx = x0 + xl;
+    if (gz >= g.od || gy >= g.oh || gx >= g.ow) continue;
+    const long long i = ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * CO + c0;
+    const v4f lo = *(const v4f*)&stage[vl * CW + c0], hi = *(const v4f*)&stage[vl * CW + c0 + 4];
+    v8u ov = {}, mv = {}, o2, oy;
+    if (other) ov = *(const v8u*)(other + i);
+    if (MODE == 1 && mask) mv = *(const v8u*)(mask + i);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float v = e < 4 ? lo[e] : hi[e - 4];
+      if (MODE == 0) {
+        v += bias[c0 + e];
+        if (relu) v = fmaxf(v, 0.0f);
+        o2[e] = f2bf(v);
+        if (other) v += bf2f(ov[e]);
+      } else {
+        if (other) v += bf2f(ov[e]);
+        o2[e] = f2bf(v);
+        if (mask && !(bf2f(mv[e]) > 0.0f)) v = 0.0f;
       }
+      oy[e] = f2bf(v);
     }
+    if (y2) *(v8u*)(y2 + i) = o2;
+    *(v8u*)(y + i) = oy;
   }
 }
 
@@ -331,6 +408,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
                                                        uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
   constexpr int NS = CI / 16;
   constexpr int MS = 8 / NS;
+  __shared__ __attribute__((aligned(16))) float dg_stage[4 * 16 * MS * CI];  // the epilogue's staging
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
@@ -387,23 +465,13 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
 #pragma unroll
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
   }
-#pragma unroll
-  for (int m = 0; m < MS; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long v = vbase + m * 16 + 4 * quad + r;
-      if (v >= g.mi) continue;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int c = s * 16 + col;
-        const long long i = v * CI + c;
-        float val = acc[m][s][r];
-        if (add) val += bf2f(add[i]);
-        if (da) da[i] = f2bf(val);
-        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
-        dzp[i] = f2bf(val);
-      }
-    }
+  float* stage = dg_stage + wv * (16 * MS) * CI;
+  stage_acc<MS, NS>(stage, acc, quad, col);
+  __syncthreads();
+  dgrad_epilogue<MS, NS>(stage, lane, [&](int m, int xl) -> long long {
+    const long long v = vbase + m * 16 + xl;
+    return v < g.mi ? v : -1;
+  }, add, mask, da, dzp);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,6 +493,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up2(const uint16_t* __res
                                                            uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
   constexpr int NS = CI / 16;
   constexpr int MS = 8 / NS;
+  __shared__ __attribute__((aligned(16))) float dg_stage[4 * 16 * MS * CI];  // the epilogue's staging
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
   const long long vbase = ((long long)blockIdx.x * 4 + wv) * (16 * MS);
@@ -467,23 +536,13 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up2(const uint16_t* __res
 #pragma unroll
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
   }
-#pragma unroll
-  for (int m = 0; m < MS; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long v = vbase + m * 16 + 4 * quad + r;
-      if (v >= g.mi) continue;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int c = s * 16 + col;
-        const long long i = v * CI + c;
-        float val = acc[m][s][r];
-        if (add) val += bf2f(add[i]);
-        if (da) da[i] = f2bf(val);
-        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
-        dzp[i] = f2bf(val);
-      }
-    }
+  float* stage = dg_stage + wv * (16 * MS) * CI;
+  stage_acc<MS, NS>(stage, acc, quad, col);
+  __syncthreads();
+  dgrad_epilogue<MS, NS>(stage, lane, [&](int m, int xl) -> long long {
+    const long long v = vbase + m * 16 + xl;
+    return v < g.mi ? v : -1;
+  }, add, mask, da, dzp);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,22 +567,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t* __rest
                                                           const uint16_t* __restrict__ mask,
                                                           uint16_t* __restrict__ da, uint16_t* __restrict__ dzp) {
   constexpr int NS = CI / 16, MS = 8 / NS;
+  __shared__ __attribute__((aligned(16))) float dg_stage[4 * 16 * MS * CI];  // the epilogue's staging
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
-  long long t = (long long)blockIdx.x * 4 + wv;
-  if (t >= g.nwaves) return;  // per wave: the kernel has no barrier
-  const int ixt = (int)(t % g.nxt);
-  t /= g.nxt;
-  const int px = (int)(t % 2);
-  t /= 2;
-  const int yg = (int)(t % g.nyg);
-  t /= g.nyg;
-  const int qz = (int)(t % g.d);
-  const int n = (int)(t / g.d);
+  // wave index in 32 bits (the host checks nwaves < 2^31); a wave past the
+  // last one computes nothing but takes part in the epilogue's barrier
+  unsigned t = blockIdx.x * 4u + (unsigned)wv;
+  const bool active = t < (unsigned)g.nwaves;
+  if (!active) t = 0;
+  const int ixt = (int)(t % (unsigned)g.nxt);
+  t /= (unsigned)g.nxt;
+  const int px = (int)(t & 1u);
+  t >>= 1;
+  const int yg = (int)(t % (unsigned)g.nyg);
+  t /= (unsigned)g.nyg;
+  const int qz = (int)(t % (unsigned)g.d);
+  const int n = (int)(t / (unsigned)g.d);
   const int py = yg & 1, y0 = (yg >> 1) * (2 * MS) + py, i0 = ixt * 16;
   const int pz_odd = qz & 1;
-  const int nxk = px ? 2 : 1, nyk = py ? 2 : 1, nzk = pz_odd ? 2 : 1;
-  const int K = nxk * nyk * nzk * g.co, osh = ilog2(g.co);
+  // taps per axis: 2 on an odd coordinate, 1 on an even one (log2: the parity)
+  const int K = active ? g.co << (px + py + pz_odd) : 0, osh = ilog2(g.co);
   const int qx = 2 * (i0 + col) + px;  // this lane's A row
   v4f acc[MS][NS];
 #pragma unroll
@@ -535,17 +598,18 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t* __rest
     const int k = k0 + 8 * quad;
     const bool kin = k < K;
     const int ti = kin ? (k >> osh) : 0, o = k - (ti << osh);
-    const int tx = ti % nxk, ty = (ti / nxk) % nyk, tz = ti / (nxk * nyk);
+    const int tx = ti & px, ty = (ti >> px) & py, tz = ti >> (px + py);
     const int kx = px ? 2 * tx : 1, ky = py ? 2 * ty : 1, kz = pz_odd ? 2 * tz : 1;
     const int tap = (kz * 3 + ky) * 3 + kx;
     const int pz = (qz + 1 - kz) >> 1, ppx = (qx + 1 - kx) >> 1;
     const bool okx = kin && qx < g.w && ppx >= 0 && ppx < g.ow && pz >= 0 && pz < g.od;
+    const int vrow = ((n * g.od + pz) * g.oh) * g.ow + ppx;  // voxel index of row ppy = 0 (< 2^31)
     v8bf a[MS], b[NS];
 #pragma unroll
     for (int m = 0; m < MS; ++m) {
       const int qy = y0 + 2 * m, ppy = (qy + 1 - ky) >> 1;
       const bool v = okx && qy < g.h && ppy >= 0 && ppy < g.oh;
-      a[m] = v ? ld8(dz + ((((long long)n * g.od + pz) * g.oh + ppy) * g.ow + ppx) * g.co + o) : zero;
+      a[m] = v ? ld8(dz + (long long)(vrow + ppy * g.ow) * g.co + o) : zero;
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -556,26 +620,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t* __rest
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
   }
   // lane holds D[4 quad + r][col]: voxel i0 + 4 quad + r of row m, channel s*16 + col
-#pragma unroll
-  for (int m = 0; m < MS; ++m) {
-    const int qy = y0 + 2 * m;
-    if (qy >= g.h) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int qxx = 2 * (i0 + 4 * quad + r) + px;
-      if (qxx >= g.w) continue;
-      const long long v = (((long long)n * g.d + qz) * g.h + qy) * g.w + qxx;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const long long i = v * CI + s * 16 + col;
-        float val = acc[m][s][r];
-        if (add) val += bf2f(add[i]);
-        if (da) da[i] = f2bf(val);
-        if (mask && !(bf2f(mask[i]) > 0.0f)) val = 0.0f;
-        dzp[i] = f2bf(val);
-      }
-    }
-  }
+  float* stage = dg_stage + wv * (16 * MS) * CI;
+  stage_acc<MS, NS>(stage, acc, quad, col);
+  __syncthreads();
+  dgrad_epilogue<MS, NS>(stage, lane, [&](int m, int xl) -> long long {
+    const int qy = y0 + 2 * m, qxx = 2 * (i0 + xl) + px;
+    if (!active || qy >= g.h || qxx >= g.w) return -1;
+    return (((long long)n * g.d + qz) * g.h + qy) * g.w + qxx;
+  }, add, mask, da, dzp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1149,7 +1201,7 @@ void launch_bwd_data_s2(const Geo& g, const uint16_t* dz, const uint16_t* wf, co
   s2.co = g.co;
   s2.nxt = ((g.w + 1) / 2 + 15) / 16;
   s2.nyg = 2 * (((g.h + 1) / 2 + MS - 1) / MS);
-  s2.nwaves = (long long)s2.nxt * 2 * s2.nyg * g.d * g.n;
+  s2.nwaves = (long long)s2.nxt * 2 * s2.nyg * g.d * g.n;  // < 2^31: checked by sg_conv3d_bwd_data
   hipLaunchKernelGGL((k_conv_bwd_data_s2<CI>), dim3(blocks_for(s2.nwaves, 4)), dim3(256), 0, st, dz, wf, s2, add,
                      mask, da, dzp);
 }
@@ -1263,7 +1315,7 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
                                                          float* __restrict__ part, float* __restrict__ dbpart) {
   using T = WHalo<CO, CI>;
   constexpr int NO = T::NO, NC = T::NC, TZ = T::TZ, TY = T::TY, R = T::R;
-  constexpr int HX = T::HX, HXP = T::HXP, HY = T::HY, HZ = T::HZ, DZS = T::DZS, XCS = T::XCS;
+  constexpr int HXP = T::HXP, HY = T::HY, HZ = T::HZ, DZS = T::DZS, XCS = T::XCS;
   __shared__ __attribute__((aligned(16))) uint16_t dzT[T::DZ_ELEMS];
   __shared__ __attribute__((aligned(16))) uint16_t xT[T::X_ELEMS];
   const int lane = threadIdx.x & 63, kz = threadIdx.x >> 6;
@@ -1509,6 +1561,8 @@ int sg_conv3d_bwd_data(const uint16_t* dz, int n, int d, int h, int w, int ci, c
     launch_halo<1>(n, d, h, w, ci, dz, wgt_f, nullptr, add, mask, dzp, da, 0, st);
     return check_launch("sg_conv3d_bwd_data");
   }
+  if (stride == 2 && (g.mi >= (1LL << 31) || g.mo >= (1LL << 31)))
+    return fail(SG_EINVAL, "stride-2 data gradient: more than 2^31 voxels");
   if (stride == 1 && up == 1) launch_bwd_data_su<1, 1>(g, dz, wgt_f, add, mask, da, dzp, st);
   else if (stride == 2 && g.ci == 16) launch_bwd_data_s2<16>(g, dz, wgt_f, add, mask, da, dzp, st);
   else if (stride == 2 && g.ci == 32) launch_bwd_data_s2<32>(g, dz, wgt_f, add, mask, da, dzp, st);
