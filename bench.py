@@ -23,11 +23,14 @@ METRIC = "MLUPS + % HBM roofline; FP16-stored & batched vs FP32 at ≤1e-3 φ er
 
 def algorithmic_bytes_per_node(q: int, d: int, pop_bytes: int):
     """Bytes each lattice update must move (populations read and written once,
-    velocity state read and written once, phi written once and read once).
+    velocity state read and written once, phi written once and read once;
+    the 16-bit forms also read the previous step's phi, against which the
+    stored values were encoded, in both kernels).
     Returns (whole step, fused step kernel, phase-field pass)."""
-    kstep = 2 * 2 * q * pop_bytes + 2 * d * 4 + 4
-    kphi = q * pop_bytes + 4
-    return 2 * 2 * q * pop_bytes + 2 * d * 4 + 8, kstep, kphi
+    ref = 4 if pop_bytes == 2 else 0
+    kstep = 2 * 2 * q * pop_bytes + 2 * d * 4 + 4 + ref
+    kphi = q * pop_bytes + 4 + ref
+    return 2 * 2 * q * pop_bytes + 2 * d * 4 + 8 + ref, kstep, kphi
 
 
 def run_gpu(cfg, phi0, u0, storage, steps, warmup, tile=None, autotune=True, zchunk=None, bpc=None):

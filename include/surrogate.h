@@ -71,7 +71,7 @@ size_t sg_conv3d_bwd_weight_workspace(int n, int d, int h, int w, int ci, int co
 /* Weight and bias gradients: dw [co][27][ci] = sum over output voxels of
  * dz[v, o] X[n, s p + k - 1, c]; db [co] = sum of dz.  x [n, d, h, w, ci],
  * dz [n, od, oh, ow, co]; ws of at least the size above.  Summation order
- * is fixed (split over voxel chunks, partials added in chunk order), so the
+ * is fixed (split over voxel chunks, partials added in a fixed order), so the
  * result is deterministic.  Overwrites dw and db. */
 int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, const uint16_t* dz, int co,
                          int stride, int up, void* ws, size_t ws_bytes, float* dw, float* db, void* stream);

@@ -879,26 +879,33 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_taps(const uint16_t* __restr
 __global__ __launch_bounds__(256) void k_bwd_w_reduce(const float* __restrict__ part,
                                                       const float* __restrict__ dbpart, int nchunk, int co, int ci,
                                                       float* __restrict__ dw, float* __restrict__ db) {
-  __shared__ float sh[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // 16 outputs per block, the chunks split over 16 groups of lanes (group g
+  // sums chunks g, g + 16, ... in order), the 16 group sums added in group
+  // order: a fixed summation order, so the result is deterministic.  The
+  // blocks past the weights' sum the bias partials.
+  __shared__ float sh[16][17];
+  const int e = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int n = 27 * co * ci;
-  const int nb = (n + 63) / 64;
-  const bool bias = blockIdx.x == nb;  // the last block sums the bias partials
-  const int i = blockIdx.x * 64 + lane;
+  const int nb = (n + 15) / 16;
+  const bool bias = (int)blockIdx.x >= nb;
+  const int i = (bias ? (int)blockIdx.x - nb : (int)blockIdx.x) * 16 + e;
+  const int lim = bias ? co : n;
+  const float* src = bias ? dbpart : part;
+  const long long stride = bias ? co : n;
   float s = 0.0f;
-  if (bias) {
-    if (lane < co)
-      for (int k = wv; k < nchunk; k += 4) s += dbpart[(long long)k * co + lane];
-  } else if (i < n) {
-    for (int k = wv; k < nchunk; k += 4) s += part[(long long)k * n + i];
+  if (i < lim) {
+#pragma unroll 4
+    for (int k = grp; k < nchunk; k += 16) s += src[(long long)k * stride + i];
   }
-  sh[wv][lane] = s;
+  sh[grp][e] = s;
   __syncthreads();
-  if (wv != 0) return;
-  const float t = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (grp != 0 || i >= lim) return;
+  float t = 0.0f;
+#pragma unroll
+  for (int g = 0; g < 16; ++g) t += sh[g][e];
   if (bias) {
-    if (lane < co) db[lane] = t;
-  } else if (i < n) {
+    db[i] = t;
+  } else {
     const int c = i % ci, o = (i / ci) % co, tap = i / (ci * co);
     dw[((long long)o * 27 + tap) * ci + c] = t;
   }
@@ -1599,8 +1606,8 @@ int sg_conv3d_bwd_weight(const uint16_t* x, int n, int d, int h, int w, int ci, 
   else if (stride == 2) launch_bwd_w_su<2, 1>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   else launch_bwd_w_su<1, 2>(g, x, dz, nchunk, vchunk, part, dbpart, st);
   const int nred = 27 * co * ci;
-  hipLaunchKernelGGL(k_bwd_w_reduce, dim3((nred + 63) / 64 + 1), dim3(256), 0, st, part, dbpart, nchunk, co, ci,
-                     dw, db);
+  hipLaunchKernelGGL(k_bwd_w_reduce, dim3((nred + 15) / 16 + (co + 15) / 16), dim3(256), 0, st, part, dbpart, nchunk,
+                     co, ci, dw, db);
   return check_launch("sg_conv3d_bwd_weight");
 }
 
