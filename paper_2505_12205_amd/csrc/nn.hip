@@ -222,6 +222,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
   }
 }
 
+// Work item of block b of nb when consecutive blocks are dealt round-robin to
+// the 8 XCDs: the blocks of one XCD take consecutive items (a tail of fewer
+// than 8 blocks keeps its own index), so the halos that neighbouring tiles
+// share are read while they are in that XCD's L2.
+__device__ __forceinline__ int xcd_item(int b, int nb) {
+  const int full = nb & ~7;
+  return b >= full ? b : (b & 7) * (full >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // stride-1 convolution from an LDS halo tile (C channels in and out)
 // ---------------------------------------------------------------------------
@@ -260,7 +269,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   // four waves' accumulators: the larger of the two
   constexpr int STAGE_ELEMS = 4 * 16 * MS * 16 * NS * 2;
   __shared__ __attribute__((aligned(16))) uint16_t halo[T::ELEMS > STAGE_ELEMS ? T::ELEMS : STAGE_ELEMS];
-  int b = blockIdx.x;
+  int b = xcd_item(blockIdx.x, gridDim.x);
   const int tx = b % g.ntx;
   b /= g.ntx;
   const int ty = b % g.nty;
@@ -269,15 +278,24 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   const int n = b / g.ntz;
   const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
   // stage the brick and its halo, zero outside the grid; the staged origin
-  // is one input voxel before the brick (x0, y0, z0 are even for U = 2)
-  for (int i = threadIdx.x; i < HZ * HY * HX * (CI / 8); i += 256) {
+  // is one input voxel before the brick (x0, y0, z0 are even for U = 2).
+  // Every load of a thread is issued before the first LDS write.
+  constexpr int NITEMS = HZ * HY * HX * (CI / 8), PT = (NITEMS + 255) / 256;
+  v8bf val[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int i = threadIdx.x + 256 * k;
     const int c8 = (i % (CI / 8)) * 8, vox = i / (CI / 8);
     const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
     const int gx = x0 / U - 1 + hx, gy = y0 / U - 1 + hy, gz = z0 / U - 1 + hz;
-    v8bf val = {};
-    if (gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
-      val = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * CI + c8);
-    *(v8bf*)&halo[vox * CI + c8] = val;
+    val[k] = (v8bf){};
+    if ((NITEMS % 256 == 0 || i < NITEMS) && gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
+      val[k] = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * CI + c8);
+  }
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (NITEMS % 256 == 0 || i < NITEMS) *(v8bf*)&halo[i * 8] = val[k];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1285,22 +1303,30 @@ void launch_halo(int n, int d, int h, int w, int c, const uint16_t* x, const uin
 // stages dz transposed (channel-major, dzT[o][row][x]) and the input with a
 // one-voxel halo transposed (xT[c][hz][hy][hx], in upsampled coordinates for
 // U = 2), once.  Wave w owns the nine taps with kz = w: per 32-voxel K step
-// it reads the dz operand once and, for each ky, one halo row segment
-// (two aligned 16-byte reads) from which the three kx shifts are cut with
-// byte alignment -- dW[o][tap][c] += dz[p][o] X[p + tap - 1][c].  Layers of
-// 64 channels are split into 32-channel slices of co and ci (blockIdx.y).
-// The per-block sums go to the same partial layout as the direct kernels.
+// it reads the dz operand and one new halo row segment (two aligned 16-byte
+// reads, from which the three kx shifts are cut with byte alignment), and
+// keeps the rows of the three ky taps in registers --
+// dW[o][tap][c] += dz[p][o] X[p + tap - 1][c].  Layers are split into slices
+// of 16 output channels and at most 32 input channels (blockIdx.y), which
+// keeps a wave's accumulators and rows within 256 registers (two waves per
+// SIMD).  The per-block sums go to the same partial layout as the direct
+// kernels.
 template <int CO, int CI>
 struct WHalo {
+  static_assert(CO == 16 && (CI == 16 || CI == 32), "slices of 16 output and 16 or 32 input channels");
   static constexpr int NO = CO / 16, NC = CI / 16;
-  static constexpr int TZ = CI == 16 ? 4 : 2, TY = (CI == 32 && CO == 32) ? 4 : 8;
+  static constexpr int TZ = CI == 16 ? 4 : 2, TY = 8;
   static constexpr int R = TZ * TY;                 // rows of 16 voxels
+  static_assert(TZ % 2 == 0, "the K step pairs rows of adjacent z planes");
   static constexpr int HX = 18, HXP = 24, HY = TY + 2, HZ = TZ + 2;
   static_assert(HXP >= 20, "halo rows are staged 20 wide");
   static constexpr int DZS = R * 16 + 8;            // dzT channel stride (elements), 4 banks apart
   static constexpr int XB = HZ * HY * HXP;          // halo elements per channel
   static constexpr int XCS = XB + 2 * ((20 - (XB / 2) % 64 + 64) % 64);  // 20 banks apart
   static constexpr int DZ_ELEMS = CO * DZS, X_ELEMS = CI * XCS;
+  // the 16-channel slice has the registers to load the next brick while it
+  // multiplies the current one
+  static constexpr bool PF = CI == 16;
 };
 constexpr int kWHaloBlocks = 1024;
 
@@ -1316,8 +1342,8 @@ __device__ __forceinline__ v8bf as_bf8(uint32_t a, uint32_t b, uint32_t c, uint3
   return __builtin_bit_cast(v8bf, v);
 }
 
-template <int CO, int CI, int U>
-__global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restrict__ x,
+template <int CO, int CI, int U, bool PF>
+__global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_bwd_w_halo(const uint16_t* __restrict__ x,
                                                          const uint16_t* __restrict__ dz, WGeo g, int cot, int cit,
                                                          float* __restrict__ part, float* __restrict__ dbpart) {
   using T = WHalo<CO, CI>;
@@ -1339,7 +1365,15 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
   v8bf ones;
 #pragma unroll
   for (int j = 0; j < 8; ++j) ones[j] = (__bf16)1.0f;
-  for (int b = blockIdx.x; b < g.nbricks; b += gridDim.x) {
+  // Staging items: dz items are 4 consecutive x voxels x 8 channels of an
+  // output row, x items 4 consecutive halo voxels x 8 channels of a halo row
+  // (the halo rows are staged 20 wide, inside HXP).  Every load of a brick
+  // is issued before the first is used, into registers; with PF the next
+  // brick's loads are in flight while the current brick is multiplied.
+  constexpr int DZ_ITEMS = R * 4 * (CO / 8), X_ITEMS = HZ * HY * 5 * (CI / 8);
+  constexpr int DZ_PT = (DZ_ITEMS + 191) / 192, X_PT = (X_ITEMS + 191) / 192;
+  uint4 vd[DZ_PT][4], vx[X_PT][4];
+  auto load = [&](int b) {
     int r0 = b;
     const int tx = r0 % g.ntx;
     r0 /= g.ntx;
@@ -1348,82 +1382,119 @@ __global__ __launch_bounds__(192) void k_conv_bwd_w_halo(const uint16_t* __restr
     const int tz = r0 % g.ntz;
     const int n = r0 / g.ntz;
     const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
-    __syncthreads();  // the previous brick's reads are done
-    // transposed staging, four consecutive x voxels of one channel per
-    // 8-byte LDS write (the halo rows are staged 20 wide, inside HXP)
-    for (int i = threadIdx.x; i < R * 4 * (CO / 8); i += 192) {
+#pragma unroll
+    for (int k = 0; k < DZ_PT; ++k) {
+      const int i = threadIdx.x + 192 * k;
       const int c8 = (i % (CO / 8)) * 8, v4 = (i / (CO / 8)) * 4;
       const int gz = z0 + (v4 >> 4) / TY, gy = y0 + (v4 >> 4) % TY;
-      uint4 val[4];
+      const bool rowok = (DZ_ITEMS % 192 == 0 || i < DZ_ITEMS) && gz < g.od && gy < g.oh;
+      const long long row = (((long long)n * g.od + gz) * g.oh + gy) * g.ow;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gx = x0 + (v4 & 15) + e;
-        val[e] = (uint4){0u, 0u, 0u, 0u};
-        if (gz < g.od && gy < g.oh && gx < g.ow)
-          val[e] = *(const uint4*)(dz + ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * cot + co0 + c8);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        uint32_t h[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t w = (j >> 1) == 0 ? val[e].x : (j >> 1) == 1 ? val[e].y : (j >> 1) == 2 ? val[e].z : val[e].w;
-          h[e] = (w >> (16 * (j & 1))) & 0xFFFFu;
-        }
-        *(uint2*)&dzT[(c8 + j) * DZS + v4] = (uint2){h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        vd[k][e] = (uint4){0u, 0u, 0u, 0u};
+        if (rowok && gx < g.ow) vd[k][e] = *(const uint4*)(dz + (row + gx) * cot + co0 + c8);
       }
     }
-    for (int i = threadIdx.x; i < HZ * HY * 5 * (CI / 8); i += 192) {
+#pragma unroll
+    for (int k = 0; k < X_PT; ++k) {
+      const int i = threadIdx.x + 192 * k;
       const int c8 = (i % (CI / 8)) * 8, hv = i / (CI / 8);
       const int hx4 = (hv % 5) * 4, hy = (hv / 5) % HY, hz = hv / (5 * HY);
       const int qy = y0 - 1 + hy, qz = z0 - 1 + hz;
-      uint4 val[4];
+      const bool rowok = (X_ITEMS % 192 == 0 || i < X_ITEMS) && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od;
+      const long long row = (((long long)n * g.d + qz / U) * g.h + qy / U) * g.w;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int qx = x0 - 1 + hx4 + e;
-        val[e] = (uint4){0u, 0u, 0u, 0u};
-        if (qx >= 0 && qx < g.ow && qy >= 0 && qy < g.oh && qz >= 0 && qz < g.od)
-          val[e] = *(const uint4*)(x + ((((long long)n * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * cit + ci0 + c8);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        uint32_t h[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t w = (j >> 1) == 0 ? val[e].x : (j >> 1) == 1 ? val[e].y : (j >> 1) == 2 ? val[e].z : val[e].w;
-          h[e] = (w >> (16 * (j & 1))) & 0xFFFFu;
-        }
-        *(uint2*)&xT[(c8 + j) * XCS + (hz * HY + hy) * HXP + hx4] = (uint2){h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        vx[k][e] = (uint4){0u, 0u, 0u, 0u};
+        if (rowok && qx >= 0 && qx < g.ow) vx[k][e] = *(const uint4*)(x + (row + qx / U) * cit + ci0 + c8);
       }
     }
+  };
+  // transposed LDS writes: channel c8 + j of the item's 4 voxels in one 8-byte
+  // write; v_perm pairs the 16-bit halves of two voxels' words
+  auto put = [](uint16_t* dst, const uint4 (&v)[4], int j) {
+    const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      w[e] = (j >> 1) == 0 ? v[e].x : (j >> 1) == 1 ? v[e].y : (j >> 1) == 2 ? v[e].z : v[e].w;
+    *(uint2*)dst = (uint2){__builtin_amdgcn_perm(w[1], w[0], sel), __builtin_amdgcn_perm(w[3], w[2], sel)};
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < DZ_PT; ++k) {
+      const int i = threadIdx.x + 192 * k;
+      if (DZ_ITEMS % 192 == 0 || i < DZ_ITEMS) {
+        const int c8 = (i % (CO / 8)) * 8, v4 = (i / (CO / 8)) * 4;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) put(&dzT[(c8 + j) * DZS + v4], vd[k], j);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < X_PT; ++k) {
+      const int i = threadIdx.x + 192 * k;
+      if (X_ITEMS % 192 == 0 || i < X_ITEMS) {
+        const int c8 = (i % (CI / 8)) * 8, hv = i / (CI / 8);
+        const int hx4 = (hv % 5) * 4, hy = (hv / 5) % HY, hz = hv / (5 * HY);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) put(&xT[(c8 + j) * XCS + (hz * HY + hy) * HXP + hx4], vx[k], j);
+      }
+    }
+  };
+  // brick walk: the blocks of one XCD start on adjacent bricks (xcd_item)
+  const int G = gridDim.x;
+  const int v0 = xcd_item(blockIdx.x, G);
+  if (PF && v0 < g.nbricks) load(v0);
+  for (int b = v0; b < g.nbricks; b += G) {
+    if (!PF) load(b);
+    __syncthreads();  // the previous brick's reads are done
+    store();
     __syncthreads();
-    for (int st = 0; st < R / 2; ++st) {
-      const int r = 2 * st + (quad >> 1), xo = 8 * (quad & 1);
-      const int rz = r / TY, ry = r % TY;
-      v8bf a[NO];
+    if (PF && b + G < g.nbricks) load(b + G);
+    // K step of 32 voxels: quads 0-1 hold x 0..15 of row (2 zp, ry), quads
+    // 2-3 those of row (2 zp + 1, ry).  The halo row a lane reads for tap
+    // (kz, ky) is (2 zp + quad / 2 + kz, ry + ky), so walking ry keeps the
+    // three rows of the ky taps in registers (with their kx shifts cut
+    // once) and reads one new halo row per step.
+    const int xo = 8 * (quad & 1);
 #pragma unroll
-      for (int ot = 0; ot < NO; ++ot) a[ot] = *(const v8bf*)&dzT[(ot * 16 + col) * DZS + r * 16 + xo];
-      if (kz == 0)
-#pragma unroll
-        for (int ot = 0; ot < NO; ++ot) accb[ot] = mfma32(a[ot], ones, accb[ot]);
-#pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
+    for (int zp = 0; zp < TZ / 2; ++zp) {
+      const int rz = 2 * zp + (quad >> 1);
+      v8bf win[3][NC][3];  // [row slot][ct][kx]
+      auto ld_row = [&](int hy, v8bf (&w)[NC][3]) {
 #pragma unroll
         for (int ct = 0; ct < NC; ++ct) {
-          const uint16_t* src = &xT[(ct * 16 + col) * XCS + ((rz + kz) * HY + ry + ky) * HXP + xo];
+          const uint16_t* src = &xT[(ct * 16 + col) * XCS + ((rz + kz) * HY + hy) * HXP + xo];
           const uint4 lo = *(const uint4*)src, hi = *(const uint4*)(src + 8);
           // window elements kx .. kx + 7 of the 16 read: kx = 1 shifts by one bf16
-          const v8bf b0 = as_bf8(lo.x, lo.y, lo.z, lo.w);
-          const v8bf b1 = as_bf8(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
-                                 __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi.x, lo.w, 2));
-          const v8bf b2 = as_bf8(lo.y, lo.z, lo.w, hi.x);
-#pragma unroll
-          for (int ot = 0; ot < NO; ++ot) {
-            acc[ky * 3 + 0][ot * NC + ct] = mfma32(a[ot], b0, acc[ky * 3 + 0][ot * NC + ct]);
-            acc[ky * 3 + 1][ot * NC + ct] = mfma32(a[ot], b1, acc[ky * 3 + 1][ot * NC + ct]);
-            acc[ky * 3 + 2][ot * NC + ct] = mfma32(a[ot], b2, acc[ky * 3 + 2][ot * NC + ct]);
-          }
+          w[ct][0] = as_bf8(lo.x, lo.y, lo.z, lo.w);
+          w[ct][1] = as_bf8(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                            __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi.x, lo.w, 2));
+          w[ct][2] = as_bf8(lo.y, lo.z, lo.w, hi.x);
         }
+      };
+      ld_row(0, win[0]);
+      ld_row(1, win[1]);
+#pragma unroll
+      for (int ry = 0; ry < TY; ++ry) {
+        ld_row(ry + 2, win[(ry + 2) % 3]);
+        v8bf a[NO];
+#pragma unroll
+        for (int ot = 0; ot < NO; ++ot) a[ot] = *(const v8bf*)&dzT[(ot * 16 + col) * DZS + (rz * TY + ry) * 16 + xo];
+        if (kz == 0)
+#pragma unroll
+          for (int ot = 0; ot < NO; ++ot) accb[ot] = mfma32(a[ot], ones, accb[ot]);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct)
+#pragma unroll
+            for (int ot = 0; ot < NO; ++ot)
+#pragma unroll
+              for (int kx = 0; kx < 3; ++kx)
+                acc[ky * 3 + kx][ot * NC + ct] = mfma32(a[ot], win[(ry + ky) % 3][ct][kx], acc[ky * 3 + kx][ot * NC + ct]);
       }
     }
   }
@@ -1471,10 +1542,9 @@ WGeo whalo_geo(const Geo& g) {
   return w;
 }
 
-// the slice shape of a layer: min(channels, 32) for co and ci
+// the slice shape of a layer: 16 output channels, min(ci, 32) input channels
 WGeo whalo_geo_of(const Geo& g) {
-  if (g.ci == 16) return g.co == 16 ? whalo_geo<16, 16>(g) : whalo_geo<32, 16>(g);
-  return g.co == 16 ? whalo_geo<16, 32>(g) : whalo_geo<32, 32>(g);
+  return g.ci == 16 ? whalo_geo<16, 16>(g) : whalo_geo<16, 32>(g);
 }
 
 template <int CO, int CI>
@@ -1482,27 +1552,25 @@ void launch_whalo_c(const Geo& g, int up, const uint16_t* x, const uint16_t* dz,
                     float* dbpart, hipStream_t st) {
   const WGeo w = whalo_geo<CO, CI>(g);
   const dim3 grid(nchunk, (g.co / CO) * (g.ci / CI));
+  constexpr bool PF = WHalo<CO, CI>::PF;
   if (up == 1)
-    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 1>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part, dbpart);
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 1, PF>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part,
+                       dbpart);
   else
-    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 2>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part, dbpart);
+    hipLaunchKernelGGL((k_conv_bwd_w_halo<CO, CI, 2, PF>), grid, dim3(192), 0, st, x, dz, w, g.co, g.ci, part,
+                       dbpart);
 }
 
 void launch_whalo(const Geo& g, int up, const uint16_t* x, const uint16_t* dz, int nchunk, float* part,
                   float* dbpart, hipStream_t st) {
-  if (g.ci == 16) {
-    if (g.co == 16) launch_whalo_c<16, 16>(g, up, x, dz, nchunk, part, dbpart, st);
-    else launch_whalo_c<32, 16>(g, up, x, dz, nchunk, part, dbpart, st);
-  } else {
-    if (g.co == 16) launch_whalo_c<16, 32>(g, up, x, dz, nchunk, part, dbpart, st);
-    else launch_whalo_c<32, 32>(g, up, x, dz, nchunk, part, dbpart, st);
-  }
+  if (g.ci == 16) launch_whalo_c<16, 16>(g, up, x, dz, nchunk, part, dbpart, st);
+  else launch_whalo_c<16, 32>(g, up, x, dz, nchunk, part, dbpart, st);
 }
 
 void wchunks(const Geo& g, int stride, int& nchunk, long long& vchunk) {
   if (whalo_ok(g, stride)) {  // one chunk per block of the brick walk, ~1024 blocks over the slices
     const long long nb = whalo_geo_of(g).nbricks;
-    const int slices = (g.co / std::min(g.co, 32)) * (g.ci / std::min(g.ci, 32));
+    const int slices = (g.co / 16) * (g.ci / std::min(g.ci, 32));
     const int cap = kWHaloBlocks / slices;
     nchunk = (int)(nb < cap ? nb : cap);
     if (nchunk < 1) nchunk = 1;
