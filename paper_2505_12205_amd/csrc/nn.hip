@@ -41,9 +41,15 @@ int check_launch(const char* what) {
 }
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
-  const uint32_t u = __float_as_uint(v);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+// float -> bf16 rounded to nearest even: gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32), two values per instruction in f2bf2
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, (v2bf){(__bf16)lo, (__bf16)hi});
+}
+__device__ __forceinline__ uint4 f2bf8(const float (&v)[8]) {
+  return (uint4){f2bf2(v[0], v[1]), f2bf2(v[2], v[3]), f2bf2(v[4], v[5]), f2bf2(v[6], v[7])};
 }
 
 __device__ __forceinline__ v4s ld4(const uint16_t* p) { return *(const v4s*)p; }
@@ -117,19 +123,20 @@ __device__ __forceinline__ void dgrad_epilogue(const float* stage, int lane, Vox
     if (v < 0) continue;
     const long long i = v * CW + c0;
     const v4f lo = *(const v4f*)&stage[vl * CW + c0], hi = *(const v4f*)&stage[vl * CW + c0 + 4];
-    v8u av = {}, mv = {}, od, oz;
+    v8u av = {}, mv = {};
+    float od[8], oz[8];
     if (add) av = *(const v8u*)(add + i);
     if (mask) mv = *(const v8u*)(mask + i);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       float val = e < 4 ? lo[e] : hi[e - 4];
       if (add) val += bf2f(av[e]);
-      od[e] = f2bf(val);
+      od[e] = val;
       if (mask && !(bf2f(mv[e]) > 0.0f)) val = 0.0f;
-      oz[e] = f2bf(val);
+      oz[e] = val;
     }
-    if (da) *(v8u*)(da + i) = od;
-    *(v8u*)(dzp + i) = oz;
+    if (da) *(uint4*)(da + i) = f2bf8(od);
+    *(uint4*)(dzp + i) = f2bf8(oz);
   }
 }
 
@@ -207,18 +214,19 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
     if (v >= g.mo) continue;
     const long long i = v * CO + c0;
     const v4f lo = *(const v4f*)&stage[vl * CO + c0], hi = *(const v4f*)&stage[vl * CO + c0 + 4];
-    v8u sv = {}, orr, oy;
+    v8u sv = {};
+    float orr[8], oy[8];
     if (skip) sv = *(const v8u*)(skip + i);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       float val = (e < 4 ? lo[e] : hi[e - 4]) + bias[c0 + e];
       if (relu) val = fmaxf(val, 0.0f);
-      orr[e] = f2bf(val);
+      orr[e] = val;
       if (skip) val += bf2f(sv[e]);
-      oy[e] = f2bf(val);
+      oy[e] = val;
     }
-    if (yr) *(v8u*)(yr + i) = orr;
-    *(v8u*)(y + i) = oy;
+    if (yr) *(uint4*)(yr + i) = f2bf8(orr);
+    *(uint4*)(y + i) = f2bf8(oy);
   }
 }
 
@@ -279,18 +287,22 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   const int x0 = tx * 16, y0 = ty * TY, z0 = tz * TZ;
   // stage the brick and its halo, zero outside the grid; the staged origin
   // is one input voxel before the brick (x0, y0, z0 are even for U = 2).
-  // Every load of a thread is issued before the first LDS write.
-  constexpr int NITEMS = HZ * HY * HX * (CI / 8), PT = (NITEMS + 255) / 256;
+  // Every load of a thread is issued before the first LDS write.  Item i is
+  // 8 channels of one staged voxel, row-major over the staged rows of HX
+  // voxels; its global offset is that of the staged origin plus the row's
+  // and the voxel's.
+  constexpr int CG = CI / 8, RW = HX * CG, NITEMS = HZ * HY * RW, PT = (NITEMS + 255) / 256;
+  const int sz0 = z0 / U - 1, sy0 = y0 / U - 1, sx0 = x0 / U - 1;
+  const long long obase = (((long long)n * g.d + sz0) * g.h + sy0) * g.w + sx0;  // may lie before x: offset only
   v8bf val[PT];
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
     const int i = threadIdx.x + 256 * k;
-    const int c8 = (i % (CI / 8)) * 8, vox = i / (CI / 8);
-    const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-    const int gx = x0 / U - 1 + hx, gy = y0 / U - 1 + hy, gz = z0 / U - 1 + hz;
+    const int row = i / RW, e = i - row * RW, hz = row / HY, hy = row - hz * HY, hx = e / CG;
+    const bool in = (NITEMS % 256 == 0 || i < NITEMS) && (unsigned)(sz0 + hz) < (unsigned)g.d &&
+                    (unsigned)(sy0 + hy) < (unsigned)g.h && (unsigned)(sx0 + hx) < (unsigned)g.w;
     val[k] = (v8bf){};
-    if ((NITEMS % 256 == 0 || i < NITEMS) && gx >= 0 && gx < g.w && gy >= 0 && gy < g.h && gz >= 0 && gz < g.d)
-      val[k] = ld8(x + ((((long long)n * g.d + gz) * g.h + gy) * g.w + gx) * CI + c8);
+    if (in) val[k] = ld8(x + (obase + (long long)(hz * g.h + hy) * g.w + hx) * CI + (e - hx * CG) * 8);
   }
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
@@ -392,7 +404,8 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     if (gz >= g.od || gy >= g.oh || gx >= g.ow) continue;
     const long long i = ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * CO + c0;
     const v4f lo = *(const v4f*)&stage[vl * CW + c0], hi = *(const v4f*)&stage[vl * CW + c0 + 4];
-    v8u ov = {}, mv = {}, o2, oy;
+    v8u ov = {}, mv = {};
+    float o2[8], oy[8];
     if (other) ov = *(const v8u*)(other + i);
     if (MODE == 1 && mask) mv = *(const v8u*)(mask + i);
 #pragma unroll
@@ -401,17 +414,17 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
       if (MODE == 0) {
         v += bias[c0 + e];
         if (relu) v = fmaxf(v, 0.0f);
-        o2[e] = f2bf(v);
+        o2[e] = v;
         if (other) v += bf2f(ov[e]);
       } else {
         if (other) v += bf2f(ov[e]);
-        o2[e] = f2bf(v);
+        o2[e] = v;
         if (mask && !(bf2f(mv[e]) > 0.0f)) v = 0.0f;
       }
-      oy[e] = f2bf(v);
+      oy[e] = v;
     }
-    if (y2) *(v8u*)(y2 + i) = o2;
-    *(v8u*)(y + i) = oy;
+    if (y2) *(uint4*)(y2 + i) = f2bf8(o2);
+    *(uint4*)(y + i) = f2bf8(oy);
   }
 }
 
@@ -1520,8 +1533,8 @@ __global__ __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 // voxel chunking of the weight gradient: about 2048 blocks (the per-tap
 // kernel has 27 blocks per chunk, the all-taps kernel one)
-// the halo-brick weight gradient takes every stride-1 layer (64-channel
-// layers in 32-channel slices)
+// the halo-brick weight gradient takes every stride-1 layer (in slices of 16
+// output and at most 32 input channels)
 bool whalo_ok(const Geo&, int stride) { return stride == 1; }
 
 template <int CO, int CI>
