@@ -76,7 +76,7 @@ CASES = [  # (ci, co, stride, up, n, d, h, w)
     (64, 64, 1, 1, 1, 4, 5, 6), (64, 32, 1, 2, 2, 3, 4, 5), (32, 16, 1, 2, 1, 5, 3, 4),
     (5, 16, 1, 1, 2, 6, 5, 7), (16, 5, 1, 1, 1, 5, 6, 4), (64, 16, 1, 1, 1, 9, 11, 13),
     # several LDS halo tiles / bricks along every axis, with ragged ends
-    (32, 32, 1, 1, 2, 5, 19, 37), (16, 16, 1, 1, 1, 9, 17, 33),
+    (32, 32, 1, 1, 2, 5, 19, 37), (16, 16, 1, 1, 1, 9, 17, 33), (64, 64, 1, 1, 1, 5, 11, 21),
     # every (co, ci, upsample) of the halo-brick weight gradient
     (16, 16, 1, 2, 1, 3, 5, 10), (32, 32, 1, 2, 1, 3, 5, 9), (16, 32, 1, 1, 1, 6, 9, 21),
     (32, 16, 1, 1, 2, 7, 12, 20), (16, 32, 1, 2, 1, 4, 3, 9),
