@@ -356,28 +356,48 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     if constexpr (KF < K) chunk(KF, true);
   } else {
     // x2 upsampling: the staged voxel of virtual offset t = row/col + tap - 1
-    // is floor(t / 2) + 1 along each axis.  (A separable, fully unrolled form
-    // of these addresses cut the VALU count but ran the 32 -> 16 layer 24 %
-    // slower: this loop's time is in the staging and the epilogue.)
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      const int k = k0 + 8 * quad;  // K is a multiple of 32 for CI >= 32
-      const int tap = k >> csh, c = k - (tap << csh);
-      const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
-      v8bf a[MS], bb[NS];
+    // is floor(t / 2) + 1 along each axis.  With at least 32 input channels a
+    // 32-wide K chunk lies in one tap, and a wave's rows lie in one z plane,
+    // so the tap, the staged plane and each row's staged row are
+    // wave-uniform (scalar); a lane adds only its staged x voxel and
+    // channels.  (A fully unrolled form of these addresses ran the 32 -> 16
+    // layer 24 % slower.)
+    static_assert(CI >= 32 && TY % MS == 0, "uniform taps and planes per wave");
+    const int wu = __builtin_amdgcn_readfirstlane(wv);
+    const int rz = (wu * MS) / TY, ry0 = (wu * MS) % TY;
+    const uint16_t* wrow[NS];
 #pragma unroll
-      for (int m = 0; m < MS; ++m) {
-        const int r = wv * MS + m, rz = r / TY, ry = r % TY;
+    for (int s = 0; s < NS; ++s) wrow[s] = wgt + (long long)(s * 16 + col) * K + 8 * quad;
+    // the weights of the next D chunks are in flight while a chunk multiplies
+    constexpr int D = 3, NCH = K / 32;
+    static_assert(NCH % D == 0, "whole groups of D chunks");
+    v8bf wq[D][NS];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) wq[d][s] = ld8(wrow[s] + d * 32);
+    for (int kb = 0; kb < NCH; kb += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int k0 = (kb + d) * 32;
+        const int tap = k0 >> csh, c0 = k0 - (tap << csh);
+        const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
         const int lz = ((rz + kz - 1) >> 1) + 1;
-        const int ly = ((ry + ky - 1) >> 1) + 1;
-        const int lx = ((col + kx - 1) >> 1) + 1;
-        a[m] = *(const v8bf*)&halo[((lz * HY + ly) * HX + lx) * CI + c];
+        const int xoff = (((col + kx - 1) >> 1) + 1) * CI + c0 + 8 * quad;
+        v8bf a[MS];
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+          const int ly = ((ry0 + m + ky - 1) >> 1) + 1;
+          a[m] = *(const v8bf*)&halo[(lz * HY + ly) * HX * CI + xoff];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+          for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], wq[d][s], acc[m][s]);
+        if (kb + D < NCH)
+#pragma unroll
+          for (int s = 0; s < NS; ++s) wq[d][s] = ld8(wrow[s] + k0 + D * 32);
       }
-#pragma unroll
-      for (int s = 0; s < NS; ++s) bb[s] = ld8(wgt + (long long)(s * 16 + col) * K + k);
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-#pragma unroll
-        for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
     }
   }
   // lane holds D[4 quad + r][col]: voxel x0 + 4 quad + r of row m, channel s*16 + col
