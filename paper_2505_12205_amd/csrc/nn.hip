@@ -360,8 +360,7 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     // 32-wide K chunk lies in one tap, and a wave's rows lie in one z plane,
     // so the tap, the staged plane and each row's staged row are
     // wave-uniform (scalar); a lane adds only its staged x voxel and
-    // channels.  (A fully unrolled form of these addresses ran the 32 -> 16
-    // layer 24 % slower.)
+    // channels.
     static_assert(CI >= 32 && TY % MS == 0, "uniform taps and planes per wave");
     const int wu = __builtin_amdgcn_readfirstlane(wv);
     const int rz = (wu * MS) / TY, ry0 = (wu * MS) % TY;
