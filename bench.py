@@ -178,28 +178,30 @@ def run_drops(reps=20):
             "label_Gnodes_per_s": round(n / t_label / 1e9, 2)}
 
 
-def counted_traffic(zchunk):
+def counted_traffic(zchunk, tile):
     """HBM bytes per launch of the fused FP32 step from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
-    of known size), or None when the kernel source has changed since the
-    counters were taken or the run used the other interior kernel (tiled
-    for z_chunk 0, z-marching otherwise) than the one counted."""
+    summaries (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy
+    of known size): the record of the interior kernel the run used (tiled for
+    z_chunk 0, z-marching otherwise) at the run's tile, or None when there is
+    none or the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None, None
     with open(path) as f:
-        rec = json.load(f)
+        recs = json.load(f)["records"]
     csrc = os.path.join(ROOT, "paper_2505_12205_amd", "csrc")
     h = hashlib.sha256()
     for name in ("kernels.hpp", "lattice.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
-    if h.hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
-        return None, None
-    if (zchunk > 0) != (rec.get("z_chunk", 0) > 0):
-        return None, None
-    return float(rec["traffic_bytes_per_launch"]), rec.get("summary")
+    for rec in recs:
+        if h.hexdigest()[:16] != rec.get("kernel_source_sha256_16"):
+            continue
+        if (zchunk > 0) != (rec.get("z_chunk", 0) > 0) or list(tile) != rec.get("tile"):
+            continue
+        return float(rec["traffic_bytes_per_launch"]), rec.get("summary")
+    return None, None
 
 
 def copy_probe(gib: float = 2.0, reps: int = 10):
@@ -379,7 +381,7 @@ def main():
         print(f"[bench] surrogate {forms['surrogate_bf16_mfma']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
 
-    traffic, traffic_src = counted_traffic(zchunk_used)
+    traffic, traffic_src = counted_traffic(zchunk_used, tile_used)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
