@@ -257,6 +257,9 @@ struct HaloTile {
   static constexpr int TY = ROWS >= 16 ? 8 : 4, TZ = ROWS / TY;
   static constexpr int HX = U == 1 ? 18 : 10, HY = U == 1 ? TY + 2 : TY / 2 + 2, HZ = U == 1 ? TZ + 2 : TZ / 2 + 2;
   static constexpr int ELEMS = HZ * HY * HX * CI;
+  // the tiles whose waves split the channels are held to two waves per
+  // SIMD's registers
+  static constexpr int WPE = U == 1 && NS >= 2 ? 2 : 1;
 };
 
 struct HGeo {
@@ -266,7 +269,7 @@ struct HGeo {
 };
 
 template <int CI, int CO, int U, int MODE>
-__global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ x, const uint16_t* __restrict__ wgt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HaloTile<CI, CO, U>::WPE))) void k_conv_halo(const uint16_t* __restrict__ x, const uint16_t* __restrict__ wgt,
                                                    const float* __restrict__ bias,
                                                    const uint16_t* __restrict__ other,
                                                    const uint16_t* __restrict__ mask, uint16_t* __restrict__ y,
@@ -312,11 +315,17 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
-  v4f acc[MS][NS];
+  // With 32 or 64 output channels (stride 1) the waves split the channels:
+  // wave wv takes the 16-channel slice wv % NS over MS NS rows of the tile,
+  // so it loads 1/NS of the weights per K chunk instead of all of them;
+  // otherwise a wave takes MS rows and every channel.
+  constexpr bool WS = U == 1 && NS >= 2;
+  constexpr int MW = WS ? MS * NS : MS, NW = WS ? 1 : NS;  // a wave's rows and channel tiles
+  v4f acc[MW][NW];
 #pragma unroll
-  for (int m = 0; m < MS; ++m)
+  for (int m = 0; m < MW; ++m)
 #pragma unroll
-    for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < NW; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
   constexpr int K = 27 * CI;
   constexpr int csh = CI == 16 ? 4 : (CI == 32 ? 5 : 6);
   if constexpr (U == 1) {
@@ -325,12 +334,14 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     // m * HX (a compile-time stride: an immediate LDS offset) plus the tap's
     // offset, which depends only on the K chunk and the lane's quad.  The
     // tap offsets of the chunk are wave-uniform; the lane picks one of two.
-    static_assert(TY % MS == 0, "a wave's rows lie in one z plane");
-    const int r0 = wv * MS;
+    static_assert(WS || TY % MS == 0, "a wave's rows lie in one z plane");
+    const int r0 = WS ? (wv / NS) * MW : wv * MS;
     const int abase = (((r0 / TY) * HY + r0 % TY) * HX + col) * CI;
-    const uint16_t* wrow[NS];
+    // staged offset of the wave's row m from its row 0 (compile-time)
+    auto row_off = [](int m) { return WS ? ((m / TY) * HY + m % TY) * HX * CI : m * HX * CI; };
+    const uint16_t* wrow[NW];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) wrow[s] = wgt + (long long)(s * 16 + col) * K;
+    for (int s = 0; s < NW; ++s) wrow[s] = wgt + (long long)((WS ? wv % NS : s) * 16 + col) * K;
     auto tap_off = [](int t) { return (((t / 9) * HY + (t / 3) % 3) * HX + t % 3) * CI; };
     auto chunk = [&](int k0, bool tail) {
       const int k = k0 + 8 * quad;
@@ -339,21 +350,44 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
       const int o0 = tap_off(t0), o1 = tap_off(t0 + 1);
       const int c = kin ? k - (t0 << csh) : 0;  // < 2 CI: past CI the lane's tap is t0 + 1
       const int toff = (CI == 16 && c >= CI) ? o1 + (c - CI) : o0 + c;
-      v8bf a[MS], bb[NS];
+      v8bf a[MW], bb[NW];
 #pragma unroll
-      for (int m = 0; m < MS; ++m)
-        a[m] = kin ? *(const v8bf*)&halo[abase + toff + m * HX * CI] : (v8bf){};
+      for (int m = 0; m < MW; ++m)
+        a[m] = kin ? *(const v8bf*)&halo[abase + toff + row_off(m)] : (v8bf){};
 #pragma unroll
-      for (int s = 0; s < NS; ++s) bb[s] = kin ? ld8(wrow[s] + k) : (v8bf){};
+      for (int s = 0; s < NW; ++s) bb[s] = kin ? ld8(wrow[s] + k) : (v8bf){};
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
+      for (int s = 0; s < NW; ++s)
 #pragma unroll
-        for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
+        for (int m = 0; m < MW; ++m) acc[m][s] = mfma32(a[m], bb[s], acc[m][s]);
     };
-    constexpr int KF = K / 32 * 32;  // full chunks; CI = 16 leaves a half chunk
+    if constexpr (WS) {
+      // one weight load per chunk: a rolled loop with the next D chunks'
+      // weights in flight (a full unroll hoists the LDS reads into spills)
+      constexpr int D = 3, NCH = K / 32;
+      static_assert(CI >= 32 && NCH % D == 0, "chunks within one tap, whole groups of D");
+      v8bf wq[D];
 #pragma unroll
-    for (int k0 = 0; k0 < KF; k0 += 32) chunk(k0, false);
-    if constexpr (KF < K) chunk(KF, true);
+      for (int d = 0; d < D; ++d) wq[d] = ld8(wrow[0] + d * 32 + 8 * quad);
+      for (int kb = 0; kb < NCH; kb += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int k0 = (kb + d) * 32, t0 = k0 >> csh;
+          const int toff = tap_off(t0) + (k0 - (t0 << csh)) + 8 * quad;
+          v8bf a[MW];
+#pragma unroll
+          for (int m = 0; m < MW; ++m) a[m] = *(const v8bf*)&halo[abase + toff + row_off(m)];
+#pragma unroll
+          for (int m = 0; m < MW; ++m) acc[m][0] = mfma32(a[m], wq[d], acc[m][0]);
+          if (kb + D < NCH) wq[d] = ld8(wrow[0] + k0 + D * 32 + 8 * quad);
+        }
+      }
+    } else {
+      constexpr int KF = K / 32 * 32;  // full chunks; CI = 16 leaves a half chunk
+#pragma unroll
+      for (int k0 = 0; k0 < KF; k0 += 32) chunk(k0, false);
+      if constexpr (KF < K) chunk(KF, true);
+    }
   } else {
     // x2 upsampling: the staged voxel of virtual offset t = row/col + tap - 1
     // is floor(t / 2) + 1 along each axis.  With at least 32 input channels a
@@ -400,26 +434,31 @@ __global__ __launch_bounds__(256) void k_conv_halo(const uint16_t* __restrict__ 
     }
   }
   // lane holds D[4 quad + r][col]: voxel x0 + 4 quad + r of row m, channel s*16 + col
-  constexpr int VOX = 16 * MS, CW = 16 * NS;  // a wave's voxels and channels
+  // (row r0 + m and channel (wv % NS)*16 + col when the waves split the channels)
+  constexpr int VOX = WS ? 16 * 4 * MS : 16 * MS, CW = 16 * NS;  // voxels and channels of a staging group
+  constexpr int GT = WS ? 256 : 64;  // threads of a staging group: the block, or one wave
   // Stage the accumulators through the halo's LDS (the halo is no longer
   // read), then give every lane 8 consecutive channels of one voxel: the
   // epilogue's global accesses become 16 bytes per lane, contiguous across
   // lanes, instead of 2 bytes per lane in 32-byte pieces.
   __syncthreads();
-  float* stage = (float*)halo + wv * VOX * CW;
+  float* stage = (float*)halo + (WS ? 0 : wv * VOX * CW);
 #pragma unroll
-  for (int m = 0; m < MS; ++m)
+  for (int m = 0; m < MW; ++m)
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+    for (int s = 0; s < NW; ++s)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) stage[(m * 16 + 4 * quad + r) * CW + s * 16 + col] = acc[m][s][r];
+      for (int r = 0; r < 4; ++r)
+        stage[(((WS ? (wv / NS) * MW : 0) + m) * 16 + 4 * quad + r) * CW + (WS ? wv % NS : s) * 16 + col] =
+            acc[m][s][r];
   __syncthreads();
   constexpr int G = CW / 8;  // 8-channel groups per voxel
+  const int gi = WS ? (int)threadIdx.x : lane;
 #pragma unroll
-  for (int j = 0; j < VOX * G / 64; ++j) {
-    const int f = j * 64 + lane, vl = f / G, c0 = (f % G) * 8;
+  for (int j = 0; j < VOX * G / GT; ++j) {
+    const int f = j * GT + gi, vl = f / G, c0 = (f % G) * 8;
     const int m = vl / 16, xl = vl % 16;
-    const int rr = wv * MS + m, gz = z0 + rr / TY, gy = y0 + rr % TY, gx = x0 + xl;
+    const int rr = (WS ? 0 : wv * MS) + m, gz = z0 + rr / TY, gy = y0 + rr % TY, gx = x0 + xl;
     if (gz >= g.od || gy >= g.oh || gx >= g.ow) continue;
     const long long i = ((((long long)n * g.od + gz) * g.oh + gy) * g.ow + gx) * CO + c0;
     const v4f lo = *(const v4f*)&stage[vl * CW + c0], hi = *(const v4f*)&stage[vl * CW + c0 + 4];
