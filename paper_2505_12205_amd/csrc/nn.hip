@@ -315,11 +315,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HaloTile<CI
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
-  // With 32 or 64 output channels (stride 1) the waves split the channels:
+  // With 32 or 64 output channels the waves split the channels:
   // wave wv takes the 16-channel slice wv % NS over MS NS rows of the tile,
   // so it loads 1/NS of the weights per K chunk instead of all of them;
   // otherwise a wave takes MS rows and every channel.
-  constexpr bool WS = U == 1 && NS >= 2;
+  constexpr bool WS = NS >= 2;
   constexpr int MW = WS ? MS * NS : MS, NW = WS ? 1 : NS;  // a wave's rows and channel tiles
   v4f acc[MW][NW];
 #pragma unroll
@@ -395,20 +395,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HaloTile<CI
     // so the tap, the staged plane and each row's staged row are
     // wave-uniform (scalar); a lane adds only its staged x voxel and
     // channels.
-    static_assert(CI >= 32 && TY % MS == 0, "uniform taps and planes per wave");
+    static_assert(CI >= 32 && TY % MW == 0, "uniform taps and planes per wave");
     const int wu = __builtin_amdgcn_readfirstlane(wv);
-    const int rz = (wu * MS) / TY, ry0 = (wu * MS) % TY;
-    const uint16_t* wrow[NS];
+    const int r0 = WS ? (wu / NS) * MW : wu * MS;
+    const int rz = r0 / TY, ry0 = r0 % TY;
+    const uint16_t* wrow[NW];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) wrow[s] = wgt + (long long)(s * 16 + col) * K + 8 * quad;
+    for (int s = 0; s < NW; ++s) wrow[s] = wgt + (long long)((WS ? wu % NS : s) * 16 + col) * K + 8 * quad;
     // the weights of the next D chunks are in flight while a chunk multiplies
     constexpr int D = 3, NCH = K / 32;
     static_assert(NCH % D == 0, "whole groups of D chunks");
-    v8bf wq[D][NS];
+    v8bf wq[D][NW];
 #pragma unroll
     for (int d = 0; d < D; ++d)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) wq[d][s] = ld8(wrow[s] + d * 32);
+      for (int s = 0; s < NW; ++s) wq[d][s] = ld8(wrow[s] + d * 32);
     for (int kb = 0; kb < NCH; kb += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -417,19 +418,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HaloTile<CI
         const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
         const int lz = ((rz + kz - 1) >> 1) + 1;
         const int xoff = (((col + kx - 1) >> 1) + 1) * CI + c0 + 8 * quad;
-        v8bf a[MS];
+        v8bf a[MW];
 #pragma unroll
-        for (int m = 0; m < MS; ++m) {
+        for (int m = 0; m < MW; ++m) {
           const int ly = ((ry0 + m + ky - 1) >> 1) + 1;
           a[m] = *(const v8bf*)&halo[(lz * HY + ly) * HX * CI + xoff];
         }
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
+        for (int s = 0; s < NW; ++s)
 #pragma unroll
-          for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], wq[d][s], acc[m][s]);
+          for (int m = 0; m < MW; ++m) acc[m][s] = mfma32(a[m], wq[d][s], acc[m][s]);
         if (kb + D < NCH)
 #pragma unroll
-          for (int s = 0; s < NS; ++s) wq[d][s] = ld8(wrow[s] + k0 + D * 32);
+          for (int s = 0; s < NW; ++s) wq[d][s] = ld8(wrow[s] + k0 + D * 32);
       }
     }
   }
