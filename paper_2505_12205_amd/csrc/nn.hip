@@ -178,7 +178,25 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
   // K = 27 taps x ci, tap-major; a 32-wide K chunk gives each lane 8
   // channels of one tap (16 | ci)
   const int K = 27 * g.ci, csh = ilog2(g.ci);
-  auto load = [&](int k0, v8bf* a, v8bf* b) {
+  // The chunk's weight tile (CO rows of 32 K values, row o at wgt + o K + k0,
+  // zero past K) is loaded once per block into a double-buffered LDS tile
+  // (rows padded to 40 elements: a 16-lane read of 16 bytes from 16 rows hits
+  // distinct banks) instead of once per wave; the epilogue's staging buffer
+  // holds it during the K loop.
+  constexpr int WR = 40;
+  static_assert(2 * CO * WR * 2 <= (int)sizeof(fw_stage), "weight tiles fit the staging buffer");
+  uint16_t* wl = (uint16_t*)fw_stage;
+  const int wt = threadIdx.x;  // thread wt < 4 CO loads 8 K values of row wt / 4
+  auto wload = [&](int k0) {
+    uint4 v = {0u, 0u, 0u, 0u};
+    const int k = k0 + (wt & 3) * 8;  // K is a multiple of 16: 8 values are all in or all out
+    if (wt < 4 * CO && k < K) v = *(const uint4*)(wgt + (long long)(wt >> 2) * K + k);
+    return v;
+  };
+  auto wstore = [&](int buf, uint4 v) {
+    if (wt < 4 * CO) *(uint4*)&wl[(buf * CO + (wt >> 2)) * WR + (wt & 3) * 8] = v;
+  };
+  auto load = [&](int k0, v8bf* a) {
     const int k = k0 + 8 * quad;
     const bool kin = k < K;
     const int tap = kin ? (k >> csh) : 0, c = k - (tap << csh);
@@ -190,16 +208,27 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
       a[m] = in ? ld8(x + ((((long long)nb[m] * g.d + qz / U) * g.h + qy / U) * g.w + qx / U) * g.ci + c)
                 : zero;
     }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) b[s] = kin ? ld8(wgt + (long long)(s * 16 + col) * K + k) : zero;
   };
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int nch = (K + 31) / 32;
+  uint4 wn = wload(0);
+  wstore(0, wn);
+  if (nch > 1) wn = wload(32);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * 32, buf = ch & 1;
     v8bf a[MS], b[NS];
-    load(k0, a, b);
+    load(k0, a);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) b[s] = *(const v8bf*)&wl[(buf * CO + s * 16 + col) * WR + 8 * quad];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+    if (ch + 1 < nch) {
+      wstore(buf ^ 1, wn);  // the other tile's readers passed the previous barrier
+      if (ch + 2 < nch) wn = wload(k0 + 64);
+    }
+    __syncthreads();
   }
   // lane holds D[4 quad + r][col]: voxel row 4 quad + r, channel col; staged
   // in LDS, then written 8 channels of one voxel per lane (16-byte accesses)
@@ -608,7 +637,30 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up2(const uint16_t* __res
     for (int s = 0; s < NS; ++s) acc[m][s] = (v4f){0.f, 0.f, 0.f, 0.f};
   const v8bf zero = {};
   const int K = 64 * g.co, osh = ilog2(g.co);  // a multiple of 32: no partial chunk
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  // The chunk's weight tile (CI rows of 32 K values, row c at wu + c K + k0)
+  // is loaded once per block into a double-buffered LDS tile (rows padded to
+  // 40 elements: a 16-lane read of 16 bytes from 16 rows hits distinct
+  // banks) instead of once per wave; the epilogue's staging buffer holds it
+  // during the K loop.
+  constexpr int WR = 40;
+  static_assert(2 * CI * WR * 2 <= (int)sizeof(dg_stage), "weight tiles fit the staging buffer");
+  uint16_t* wl = (uint16_t*)dg_stage;
+  const int wt = threadIdx.x;  // thread wt < 4 CI loads 8 K values of row wt / 4
+  auto wload = [&](int k0) {
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (wt < 4 * CI) v = *(const uint4*)(wu + (long long)(wt >> 2) * K + k0 + (wt & 3) * 8);
+    return v;
+  };
+  auto wstore = [&](int buf, uint4 v) {
+    if (wt < 4 * CI) *(uint4*)&wl[(buf * CI + (wt >> 2)) * WR + (wt & 3) * 8] = v;
+  };
+  const int nch = K / 32;
+  uint4 wn = wload(0);
+  wstore(0, wn);
+  if (nch > 1) wn = wload(32);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * 32, buf = ch & 1;
     const int k = k0 + 8 * quad;
     const int t = k >> osh, o = k - (t << osh);
     const int az = t >> 4, ay = (t >> 2) & 3, ax = t & 3;
@@ -620,11 +672,16 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up2(const uint16_t* __res
       a[m] = v ? ld8(dz + ((((long long)nb[m] * g.od + pz) * g.oh + py) * g.ow + px) * g.co + o) : zero;
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) b[s] = ld8(wu + ((long long)(s * 16 + col) * 64 + t) * g.co + o);
+    for (int s = 0; s < NS; ++s) b[s] = *(const v8bf*)&wl[(buf * CI + s * 16 + col) * WR + 8 * quad];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int m = 0; m < MS; ++m) acc[m][s] = mfma32(a[m], b[s], acc[m][s]);
+    if (ch + 1 < nch) {
+      wstore(buf ^ 1, wn);  // the other tile's readers passed the previous barrier
+      if (ch + 2 < nch) wn = wload(k0 + 64);
+    }
+    __syncthreads();
   }
   float* stage = dg_stage + wv * (16 * MS) * CI;
   stage_acc<MS, NS>(stage, acc, quad, col);
