@@ -830,34 +830,38 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   const short one = 0x3F80;  // bf16 1.0
   const v4s ones = {one, one, one, one};
   const int DU = g.d * U, HU = g.h * U, WU = g.w * U;
-  for (long long vt = v0; vt < v1; vt += WV) {
-    __syncthreads();
-    // lane = voxel of the tile; the waves split the channel groups
+  // lane = voxel of the tile; the waves split the channel groups (channels
+  // wv*4 + 16 i).  The next tile's dz values and gathered input are loaded
+  // while the current tile multiplies.
+  v4s dzv[CO / 16], xg[CI / 16];
+  auto fetch = [&](long long vt) {
     const long long vv0 = vt + lane;
     const bool vok = vv0 < v1;
-    // dz tile, transposed: dzT[o][voxel]
-    for (int c4 = wv * 4; c4 < CO; c4 += 16) {
-      const v4s val = vok ? ld4(dz + vv0 * CO + c4) : (v4s){0, 0, 0, 0};
-      pair_store4(dzT, c4, lane, val);
-    }
-    // gathered input of this tap, transposed: xT[c][voxel]
-    {
-      long long v = vok ? vv0 : v0;
-      const int px = (int)(v % g.ow);
-      v /= g.ow;
-      const int py = (int)(v % g.oh);
-      v /= g.oh;
-      const int pz = (int)(v % g.od);
-      const int n = (int)(v / g.od);
-      const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
-      const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
-      const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
-                                 (in ? qx / U : 0)) * CI;
-      for (int c4 = wv * 4; c4 < CI; c4 += 16) {
-        const v4s val = in ? ld4(src + c4) : (v4s){0, 0, 0, 0};
-        pair_store4(xT, c4, lane, val);
-      }
-    }
+#pragma unroll
+    for (int i = 0; i < CO / 16; ++i) dzv[i] = vok ? ld4(dz + vv0 * CO + wv * 4 + 16 * i) : (v4s){0, 0, 0, 0};
+    long long v = vok ? vv0 : v0;
+    const int px = (int)(v % g.ow);
+    v /= g.ow;
+    const int py = (int)(v % g.oh);
+    v /= g.oh;
+    const int pz = (int)(v % g.od);
+    const int n = (int)(v / g.od);
+    const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
+    const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+    const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
+                               (in ? qx / U : 0)) * CI;
+#pragma unroll
+    for (int i = 0; i < CI / 16; ++i) xg[i] = in ? ld4(src + wv * 4 + 16 * i) : (v4s){0, 0, 0, 0};
+  };
+  if (v0 < v1) fetch(v0);
+  for (long long vt = v0; vt < v1; vt += WV) {
+    __syncthreads();
+    // dz tile and the gathered input of this tap, transposed: dzT[o][voxel], xT[c][voxel]
+#pragma unroll
+    for (int i = 0; i < CO / 16; ++i) pair_store4(dzT, wv * 4 + 16 * i, lane, dzv[i]);
+#pragma unroll
+    for (int i = 0; i < CI / 16; ++i) pair_store4(xT, wv * 4 + 16 * i, lane, xg[i]);
+    if (vt + WV < v1) fetch(vt + WV);
     __syncthreads();
     const int kofs = wv * 16 + 4 * quad;  // this wave's voxel slice
     v4s a[NO], b[NC];
@@ -961,23 +965,30 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_taps(const uint16_t* __restr
     vv /= g.oh;
     const int pz = (int)(vv % g.od);
     const int n = (int)(vv / g.od);
+    // this lane's voxel of the input shifted by a tap; the next slot's gather
+    // is in flight while the current slot multiplies
+    v4s xv[CI / 4];
+    auto gather = [&](int tap) {
+      if (tap >= 27) return;
+      const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
+      const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
+      const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
+      const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
+                                 (in ? qx / U : 0)) * CI;
+#pragma unroll
+      for (int c4 = 0; c4 < CI; c4 += 4) xv[c4 / 4] = in ? ld4(src + c4) : (v4s){0, 0, 0, 0};
+    };
+    gather(wv);
 #pragma unroll
     for (int slot = 0; slot < SLOTS; ++slot) {
       const int tap = wv + 4 * slot;
       __syncthreads();  // dzT ready (slot 0) / previous slot's reads done
-      if (tap < 27) {
-        const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
-        const int qz = pz * S + kz - 1, qy = py * S + ky - 1, qx = px * S + kx - 1;
-        const bool in = vok && qz >= 0 && qz < DU && qy >= 0 && qy < HU && qx >= 0 && qx < WU;
-        const uint16_t* src = x + ((((long long)n * g.d + (in ? qz / U : 0)) * g.h + (in ? qy / U : 0)) * g.w +
-                                   (in ? qx / U : 0)) * CI;
+      if (tap < 27)
 #pragma unroll
-        for (int c4 = 0; c4 < CI; c4 += 4) {
-          const v4s val = in ? ld4(src + c4) : (v4s){0, 0, 0, 0};
+        for (int c4 = 0; c4 < CI; c4 += 4)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) myx[(c4 + j) * WP + lane] = (uint16_t)val[j];
-        }
-      }
+          for (int j = 0; j < 4; ++j) myx[(c4 + j) * WP + lane] = (uint16_t)xv[c4 / 4][j];
+      gather(tap + 4);
       __syncthreads();
       if (tap < 27) {
 #pragma unroll
